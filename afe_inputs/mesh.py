@@ -1,0 +1,218 @@
+"""Seeded periodic Voronoi meshes of a box [0, L)^3.
+
+This module only generates input geometry: it knows nothing of the AFE
+sub-grid, the basis or the scheme.  Both the CPU oracle and the HIP library
+consume the arrays it returns, each building its own sub-grid from them.
+
+Mesh arrays (all numpy, C order):
+    xyz          float64 [nv, 3]   one canonical coordinate per vertex, in [0, L)
+    face_ptr     int32   [nf + 1]  CSR offsets into face_vtx
+    face_vtx     int32   [sum]     polygon corners, cyclic, oriented outward
+                                   from the owner cell (right-hand rule)
+    face_vshift  int8    [sum, 3]  image shift of each corner: its position in
+                                   the owner's frame is xyz[v] + shift * L
+    face_cell    int32   [nf, 2]   (owner, neighbour)
+    nbr_shift    int8    [nf, 3]   neighbour seed in the owner's frame is
+                                   seeds[nbr] + nbr_shift * L
+    seeds        float64 [nc, 3]
+    box          float64           L
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.spatial import Voronoi, cKDTree
+
+
+def jittered_lattice_seeds(n: int, jitter: float, seed: int, box: float = 1.0) -> np.ndarray:
+    """n^3 seeds: lattice points ((i, j, k) + 1/2) h, h = box/n, each moved by a
+    uniform offset in [-jitter*h, +jitter*h]^3 and wrapped into the box.
+
+    Lattice order is C order over (i, j, k) with i along x (k varies fastest);
+    the jitter is drawn as one (n^3, 3) uniform array from default_rng(seed).
+    """
+    h = box / n
+    idx = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(seed)
+    jit = rng.uniform(-jitter * h, jitter * h, size=(n ** 3, 3))
+    pts = (idx + 0.5) * h + jit
+    return np.mod(pts, box)
+
+
+def uniform_seeds(m: int, seed: int, box: float = 1.0) -> np.ndarray:
+    """m seeds drawn uniformly in the box (Poisson-Voronoi statistics)."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0.0, box, size=(m, 3))
+
+
+def _images(seeds: np.ndarray, box: float, margin: float):
+    """Seeds plus the periodic images that fall within `margin` of the box."""
+    n = len(seeds)
+    pts = [seeds]
+    ids = [np.arange(n)]
+    shifts = [np.zeros((n, 3), dtype=np.int64)]
+    for sx in (-1, 0, 1):
+        for sy in (-1, 0, 1):
+            for sz in (-1, 0, 1):
+                if sx == 0 and sy == 0 and sz == 0:
+                    continue
+                s = np.array([sx, sy, sz])
+                p = seeds + s * box
+                keep = np.all((p > -margin) & (p < box + margin), axis=1)
+                pts.append(p[keep])
+                ids.append(np.nonzero(keep)[0])
+                shifts.append(np.tile(s, (int(keep.sum()), 1)))
+    return np.concatenate(pts), np.concatenate(ids), np.concatenate(shifts)
+
+
+def periodic_voronoi(seeds: np.ndarray, box: float = 1.0, margin: float | None = None,
+                     merge_tol: float = 1e-10) -> dict:
+    """Periodic Voronoi tessellation of `seeds` in [0, box)^3.
+
+    Every vertex is stored once (a single canonical coordinate in [0, box)),
+    and each face once, owned by the lower cell id; corners carry integer image
+    shifts so that both cells see bit-identical corner coordinates up to a
+    translation by a multiple of `box`.
+    """
+    seeds = np.asarray(seeds, dtype=np.float64)
+    n = len(seeds)
+    if n < 27:
+        raise ValueError("periodic Voronoi needs at least 27 seeds (no self-neighbour faces)")
+    if margin is None:
+        margin = 4.0 * box / n ** (1.0 / 3.0)
+    pts, pid, psh = _images(seeds, box, margin)
+    vor = Voronoi(pts)
+
+    # canonical vertex table: wrap every Voronoi vertex used by an original
+    # cell into [0, box) and merge copies that coincide up to merge_tol*box
+    rp = vor.ridge_points
+    own_mask = (rp[:, 0] < n) | (rp[:, 1] < n)
+    used = sorted({v for r, m in zip(vor.ridge_vertices, own_mask) if m for v in r})
+    if -1 in used:
+        raise RuntimeError("unbounded Voronoi region touches an original cell; increase margin")
+    used = np.array(used)
+    vpos = vor.vertices[used]
+    wrapped = np.mod(vpos, box)
+    wrapped[wrapped >= box] -= box
+    tree = cKDTree(wrapped, boxsize=box)
+    pairs = tree.query_pairs(merge_tol * box, output_type="ndarray")
+    parent = np.arange(len(used))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for a, b in pairs:
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            parent[max(ra, rb)] = min(ra, rb)
+    roots = np.array([find(i) for i in range(len(used))])
+    uroots, canon = np.unique(roots, return_inverse=True)
+    xyz = wrapped[uroots]
+    # distinct vertices must be well separated from merged copies
+    d, _ = cKDTree(xyz, boxsize=box).query(xyz, k=2)
+    if len(xyz) > 1 and d[:, 1].min() < 1e3 * merge_tol * box:
+        raise RuntimeError("near-coincident Voronoi vertices; choose another seed")
+    vmap = -np.ones(len(vor.vertices), dtype=np.int64)
+    vmap[used] = canon
+
+    faces = {}
+    for r, (a, b) in enumerate(rp):
+        for own, oth in ((a, b), (b, a)):
+            if own >= n:
+                continue
+            co, cn = int(pid[own]), int(pid[oth])
+            s = psh[oth] - psh[own]
+            if co == cn:
+                raise RuntimeError("self-neighbour face; mesh too coarse")
+            if co < cn:
+                key = (co, cn, tuple(int(x) for x in s))
+                if key not in faces:
+                    faces[key] = r
+    keys = sorted(faces)
+    face_ptr = [0]
+    face_vtx, face_vshift, face_cell, nbr_shift = [], [], [], []
+    for key in keys:
+        r = faces[key]
+        a, b = rp[r]
+        own = a if (a < n and pid[a] == key[0] and not psh[a].any()) else b
+        oth = b if own == a else a
+        po = pts[own]
+        pn = pts[oth]
+        nrm = pn - po
+        nrm /= np.linalg.norm(nrm)
+        vids = np.array(vor.ridge_vertices[r])
+        vp = vor.vertices[vids]
+        ctr = vp.mean(axis=0)
+        e1 = vp[0] - ctr
+        e1 -= nrm * np.dot(e1, nrm)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(nrm, e1)
+        ang = np.arctan2((vp - ctr) @ e2, (vp - ctr) @ e1)
+        order = np.argsort(ang)
+        vids, vp = vids[order], vp[order]
+        # positions in the owner's frame: owner seed is an original point
+        g = vmap[vids]
+        sh = np.rint((vp - xyz[g]) / box).astype(np.int64)
+        if np.abs(vp - (xyz[g] + sh * box)).max() > 1e-8 * box:
+            raise RuntimeError("vertex image shift mismatch")
+        face_vtx.extend(g.tolist())
+        face_vshift.extend(sh.tolist())
+        face_ptr.append(len(face_vtx))
+        face_cell.append((key[0], key[1]))
+        nbr_shift.append(key[2])
+    mesh = dict(
+        xyz=np.ascontiguousarray(xyz, dtype=np.float64),
+        face_ptr=np.array(face_ptr, dtype=np.int32),
+        face_vtx=np.array(face_vtx, dtype=np.int32),
+        face_vshift=np.array(face_vshift, dtype=np.int8).reshape(-1, 3),
+        face_cell=np.array(face_cell, dtype=np.int32).reshape(-1, 2),
+        nbr_shift=np.array(nbr_shift, dtype=np.int8).reshape(-1, 3),
+        seeds=seeds.copy(),
+        box=float(box),
+        n_cells=n,
+    )
+    _check_closed(mesh)
+    return mesh
+
+
+def _check_closed(mesh: dict) -> None:
+    """Every cell must see each of its vertices at one single image shift and
+    every edge of a cell's boundary must be used by exactly two of its faces."""
+    n = mesh["n_cells"]
+    fp, fv, fs = mesh["face_ptr"], mesh["face_vtx"], mesh["face_vshift"].astype(np.int64)
+    fc, ns = mesh["face_cell"], mesh["nbr_shift"].astype(np.int64)
+    vshift = [dict() for _ in range(n)]
+    edges = [dict() for _ in range(n)]
+    for f in range(len(fc)):
+        for side in (0, 1):
+            c = int(fc[f, side])
+            corners = list(range(fp[f], fp[f + 1]))
+            if side == 1:
+                corners = corners[::-1]
+            for k, ci in enumerate(corners):
+                v = int(fv[ci])
+                s = tuple(fs[ci] - (ns[f] if side == 1 else 0))
+                if vshift[c].setdefault(v, s) != s:
+                    raise RuntimeError(f"cell {c} sees vertex {v} at two images")
+                w = int(fv[corners[(k + 1) % len(corners)]])
+                edges[c][(v, w)] = edges[c].get((v, w), 0) + 1
+    for c in range(n):
+        for (v, w), cnt in edges[c].items():
+            if cnt != 1 or edges[c].get((w, v), 0) != 1:
+                raise RuntimeError(f"cell {c} is not a closed oriented surface")
+
+
+def mesh_stats(mesh: dict) -> dict:
+    """Counts used to size buffers: faces per cell, polygon edges per cell."""
+    n = mesh["n_cells"]
+    fp, fc = mesh["face_ptr"], mesh["face_cell"]
+    nf = np.zeros(n, dtype=np.int64)
+    ne2 = np.zeros(n, dtype=np.int64)
+    for f in range(len(fc)):
+        k = fp[f + 1] - fp[f]
+        for c in fc[f]:
+            nf[c] += 1
+            ne2[c] += k
+    return dict(faces_per_cell=nf, subtets_per_cell=ne2)

@@ -1,0 +1,405 @@
+"""The ADER-AFE-DG step, written plainly in float64 (Sec. 4.2 - 4.5).
+
+Notation: cell i has sub-tets k with sub-tet node -> cell DOF map P_k (conn),
+|J_k| = |det J_k|, G_k = J_k^{-1}; reference matrices M^, K^_d, V^_d = K^_d^T,
+D^_d, Z^; time basis on N+1 Gauss-Legendre nodes tau_a with weights w_a.
+
+Readings taken where the paper is silent, garbled or inconsistent:
+
+R1 (assembly, Sec. 4.3-4.4): |P_i| printed in front of the sums of reference
+   integrals (K_t,i, K_1,i, M_i) is read as the sub-tet Jacobian weighting of
+   each term, X_i = sum_k |J_k| P_k^T X^ P_k, which is what the sum over
+   sub-tets with the Jacobian (eq:ader2) produces.
+R2 (time basis): N+1 Gauss-Legendre nodes; then M_tau = diag(w), the space-time
+   K_1,i = K_tau (x) M_i and the spatial stiffness is M_tau (x) K^_d, so
+   K_1,i^{-1} = K_tau^{-1} (x) M_i^{-1}.  Because K_tau 1 = psi(0), the F_0 term
+   gives u^n at every time node, and eq:ader4 becomes
+       q[b] = u^n - sum_a (K_tau^{-1})_{ba} M_i^{-1} R[a](q),
+       R[a] = w_a sum_k P_k^T |J_k| sum_d K^_d f*_{d,k}[a],
+   with the contravariant nodal flux f*_d = dt sum_x G_k[d, x] F_x(q, grad q).
+R3 (iteration, eq:ader4): the predictor is the fixed point of that map.  It is
+   reached by Anderson acceleration of the same map with depth m (m = 0 is
+   the plain fixed-point iteration of the paper), starting from q = u^n, and
+   stops when max|G(q) - q| <= tol * max(1, max|G(q)|); the result is G(q).
+R4 (time integrals, eqn.TAvectors): f* already holds dt, so the volume term
+   uses F*bar_d = sum_a w_a f*_d[a]; the face flux uses the physical
+   Fbar = dt sum_a w_a F(q[a]) and qbar = dt sum_a w_a q[a].
+R5 (faces, Sec. 4.4): the sum over faces runs over the cell's boundary
+   sub-triangles; each integral is 2 A_t Z^ (reference triangle area 1/2).
+   In the Rusanov flux "+" is the neighbour and "-" this cell, n outward;
+   |lambda_max| is the largest |v.n| + c over the triangle's face nodes on both
+   sides from qbar/dt and |lambda^v_max| the largest 4 mu/(3 rho) likewise with
+   each side's viscosity; one value per sub-triangle.
+R6 (detector, Sec. 4.5): the divergence is the face integral of the velocity
+   jump over the cell volume; it enters the flattener multiplied by the cell
+   diameter h_i (undivided form) so that it compares with m1 c; c_min is the
+   minimum sound speed over the face nodes on both sides; states are u^n.
+R7 (artificial viscosity, Sec. 4.5, text ends before the formula):
+   mu_i = mu + beta_i * rho_i * lambda_i * h_s, h_s = h_i / (2N+1), with rho_i
+   the cell-mean density and lambda_i the largest nodal |v| + c, i.e. the
+   viscosity for which the mesh Reynolds number is one, scaled by beta_i.
+R8 (time step, eqn.timestep): h_i = cell diameter; the max runs over all DOFs
+   with h inside it taken per cell, lambda^v = 4 mu_i / (3 rho).
+R9 (initial data): nodal interpolation of the primitive variables, converted
+   to conserved variables.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+from scipy.linalg import cho_factor, cho_solve
+
+from .physics import flux, max_eig, prim_to_cons, pressure, sound_speed, visc_eig
+from .refelem import ref_element, time_basis
+from .subgrid import build_cells, faces_of_cells
+
+
+@dataclass
+class Params:
+    gamma: float = 1.4
+    mu: float = 0.0
+    m1: float = 0.1
+    av: bool = False
+    tol: float = 1e-12
+    max_iter: int = 300
+    depth: int = 63
+
+
+@dataclass
+class StepReport:
+    iters: dict = field(default_factory=dict)
+    converged: bool = True
+    positive: bool = True
+    mu: dict = field(default_factory=dict)
+    beta: dict = field(default_factory=dict)
+    pred: dict = field(default_factory=dict)
+    ti: dict = field(default_factory=dict)
+
+
+def dof_counts(mesh: dict, N: int) -> np.ndarray:
+    """Number of cell DOFs from the sub-grid's entity counts.
+
+    Sub-grid of a cell with V vertices, F faces and E polygon edges: V + F + 1
+    vertices, 3E + V + F edges, 5E triangles, 2E sub-tets; a P_N Lagrange space
+    has N-1 nodes inside each edge, (N-1)(N-2)/2 inside each triangle and
+    (N-1)(N-2)(N-3)/6 inside each tet.
+    """
+    n = mesh["n_cells"]
+    fp = mesh["face_ptr"]
+    V = np.zeros(n, dtype=np.int64)
+    F = np.zeros(n, dtype=np.int64)
+    E = np.zeros(n, dtype=np.int64)
+    verts = [set() for _ in range(n)]
+    for f, cells in enumerate(mesh["face_cell"]):
+        k = int(fp[f + 1] - fp[f])
+        for c in cells:
+            F[c] += 1
+            E[c] += k
+            verts[c].update(int(v) for v in mesh["face_vtx"][fp[f]:fp[f + 1]])
+    E //= 2
+    V[:] = [len(s) for s in verts]
+    a = N - 1
+    return (V + F + 1) + a * (3 * E + V + F) + (a * (a - 1) // 2) * 5 * E + (a * (a - 1) * (a - 2) // 6) * 2 * E
+
+
+class Oracle:
+    """Plain implementation of one ADER-AFE-DG step on a periodic mesh.
+
+    State layout (same as the library's): SoA u[5, ndof] in cell-major order,
+    cell c owning u[:, dof_ptr[c]:dof_ptr[c+1]] in the cell's DOF numbering.
+    `cells` restricts the outputs to a subset (their neighbours, and second
+    neighbours when artificial viscosity is on, are built as needed).
+    """
+
+    def __init__(self, mesh: dict, N: int, params: Params = Params(), cells=None):
+        self.mesh = mesh
+        self.N = N
+        self.p = params
+        self.ref = ref_element(N)
+        self.tb = time_basis(N)
+        n = mesh["n_cells"]
+        self.n_cells = n
+        counts = dof_counts(mesh, N)
+        self.dof_ptr = np.concatenate([[0], np.cumsum(counts)])
+        self.ndof = int(self.dof_ptr[-1])
+        cf = faces_of_cells(mesh)
+        self.targets = list(range(n)) if cells is None else sorted(set(int(c) for c in cells))
+        paired = set(self.targets)
+        if params.av and cells is not None:
+            for c in self.targets:
+                for f, side in cf[c]:
+                    paired.add(int(mesh["face_cell"][f][1 - side]))
+        self.paired = sorted(paired)
+        self.grids = build_cells(mesh, N, self.paired)
+        for c, g in self.grids.items():
+            if g.ndof != counts[c]:
+                raise AssertionError("DOF count mismatch")
+        self._chol = {}
+        self._mass = {}
+
+    # ------------------------------------------------------------------ helpers
+    def cell_state(self, u: np.ndarray, c: int) -> np.ndarray:
+        """[ndof_c, 5] view-copy of cell c's DOFs."""
+        return u[:, self.dof_ptr[c]:self.dof_ptr[c + 1]].T.copy()
+
+    def mass(self, c: int) -> np.ndarray:
+        """M_i = sum_k |J_k| P_k^T M^ P_k (R1)."""
+        if c not in self._mass:
+            g = self.grids[c]
+            M = np.zeros((g.ndof, g.ndof))
+            for k in range(len(g.conn)):
+                idx = g.conn[k]
+                M[np.ix_(idx, idx)] += g.detJ[k] * self.ref.M_f
+            self._mass[c] = M
+        return self._mass[c]
+
+    def mass_solve(self, c: int, rhs: np.ndarray) -> np.ndarray:
+        if c not in self._chol:
+            self._chol[c] = cho_factor(self.mass(c), lower=True)
+        return cho_solve(self._chol[c], rhs)
+
+    def dof_coords(self) -> np.ndarray:
+        """[3, ndof] DOF coordinates in each cell's frame (targets only filled)."""
+        x = np.full((3, self.ndof), np.nan)
+        for c in self.targets:
+            x[:, self.dof_ptr[c]:self.dof_ptr[c + 1]] = self.grids[c].dof_x.T
+        return x
+
+    def initial_state(self, field_fn) -> np.ndarray:
+        """Nodal interpolation of primitive variables (R9), for every built cell."""
+        u = np.zeros((5, self.ndof))
+        L = self.mesh["box"]
+        for c, g in self.grids.items():
+            w = field_fn(np.mod(g.dof_x, L))
+            u[:, self.dof_ptr[c]:self.dof_ptr[c + 1]] = prim_to_cons(w, self.p.gamma).T
+        return u
+
+    # ------------------------------------------------------------ detector / AV
+    def detector(self, u: np.ndarray, c: int):
+        """beta_i and mu_i of cell c from u^n (Sec. 4.5, R6, R7)."""
+        g = self.grids[c]
+        gam = self.p.gamma
+        N = self.N
+        uc = self.cell_state(u, c)
+        zrow = self.ref.Z_f.sum(axis=0)  # int_tri phi_j
+        jump_int = 0.0
+        cmin = math.inf
+        for k in range(len(g.conn)):
+            qi = uc[g.face_dof[k]]
+            qo = self.cell_state(u, int(g.nbr[k]))[g.nbr_face_dof[k]]
+            vi = qi[:, 1:4] / qi[:, :1]
+            vo = qo[:, 1:4] / qo[:, :1]
+            jn = (vo - vi) @ g.tri_normal[k]
+            jump_int += 2.0 * g.tri_area[k] * float(zrow @ jn)
+            cmin = min(cmin, float(sound_speed(qi, gam).min()), float(sound_speed(qo, gam).min()))
+        vol = g.volume
+        div = jump_int / vol
+        m1 = self.p.m1
+        beta = min(1.0, max(0.0, -(g.h * div + m1 * cmin) / (m1 * cmin)))
+        if not self.p.av:
+            return 0.0, self.p.mu
+        rho_mean = float(self.mass(c).sum(axis=0) @ uc[:, 0]) / vol
+        lam = float(max_eig(uc, gam).max())
+        mu_c = self.p.mu + beta * rho_mean * lam * g.h / (2 * N + 1)
+        return beta, mu_c
+
+    def viscosities(self, u: np.ndarray, cells) -> dict:
+        out = {}
+        for c in cells:
+            out[c] = self.detector(u, c)[1] if self.p.av else self.p.mu
+        return out
+
+    def cfl_dt(self, u: np.ndarray, cfl: float) -> float:
+        """Time step of eqn.timestep (R8) over the target cells."""
+        N = self.N
+        mus = self.viscosities(u, self.targets)
+        hmin = min(self.grids[c].h for c in self.targets)
+        smax = 0.0
+        for c in self.targets:
+            g = self.grids[c]
+            uc = self.cell_state(u, c)
+            lam = max_eig(uc, self.p.gamma) + 2.0 * visc_eig(uc, mus[c]) * (2 * N + 1) / g.h
+            smax = max(smax, float(lam.max()))
+        return cfl * hmin / ((2 * N + 1) * smax)
+
+    # --------------------------------------------------------------- predictor
+    def _nodal_flux(self, c: int, q: np.ndarray, mu: float):
+        """Physical flux at every sub-tet node and time node: [A, K, P, 3, 5]."""
+        g = self.grids[c]
+        qk = q[:, g.conn, :]  # [A, K, P, 5]
+        grad = None
+        if mu != 0.0:
+            # grad q at node m of sub-tet k: sum_d G_k[d, x] (D^_d q_k)_m
+            ref_grad = np.einsum("dml,aklv->akmdv", self.ref.D_f, qk)
+            grad = np.einsum("kdx,akmdv->akmxv", g.G, ref_grad)
+        return flux(qk, self.p.gamma, mu, grad)
+
+    def _contravariant(self, c: int, F: np.ndarray, dt: float) -> np.ndarray:
+        """f*_d = dt sum_x G_k[d, x] F_x  (eq:modified_fluxes): [A, K, P, 3, 5]."""
+        return dt * np.einsum("kdx,akpxv->akpdv", self.grids[c].G, F)
+
+    def predictor_map(self, c: int, q: np.ndarray, un: np.ndarray, dt: float, mu: float) -> np.ndarray:
+        """One application of eq:ader4 (R2): q [A, ndof, 5] -> [A, ndof, 5]."""
+        g = self.grids[c]
+        A = self.tb.nt
+        fstar = self._contravariant(c, self._nodal_flux(c, q, mu), dt)
+        # r_k[a] = w_a |J_k| sum_d K^_d f*_d  ->  [A, K, P, 5]
+        r = np.einsum("a,k,dmp,akpdv->akmv", self.tb.w, g.detJ, self.ref.K_f, fstar)
+        Rg = np.zeros((A, g.ndof, 5))
+        for a in range(A):
+            np.add.at(Rg[a], g.conn, r[a])
+        S = self.mass_solve(c, Rg.transpose(1, 0, 2).reshape(g.ndof, A * 5))
+        S = S.reshape(g.ndof, A, 5).transpose(1, 0, 2)
+        return un[None, :, :] - np.einsum("ba,anv->bnv", self.tb.K_tau_inv, S)
+
+    def predictor(self, c: int, un: np.ndarray, dt: float, mu: float, depth=None, tol=None, max_iter=None):
+        """Fixed point of eq:ader4 by Anderson(depth) iteration (R3).
+
+        Returns (q [A, ndof, 5], iterations, converged)."""
+        depth = self.p.depth if depth is None else depth
+        tol = self.p.tol if tol is None else tol
+        max_iter = self.p.max_iter if max_iter is None else max_iter
+        A = self.tb.nt
+        x = np.broadcast_to(un, (A,) + un.shape).copy()
+        Fh, Gh = [], []
+        for it in range(max_iter):
+            gx = self.predictor_map(c, x, un, dt, mu)
+            f = gx - x
+            if np.abs(f).max() <= tol * max(1.0, np.abs(gx).max()):
+                return gx, it + 1, True
+            if depth == 0:
+                x = gx
+                continue
+            Fh.append(f.ravel())
+            Gh.append(gx.ravel())
+            if len(Fh) > depth + 1:
+                Fh.pop(0)
+                Gh.pop(0)
+            if len(Fh) == 1:
+                x = gx
+                continue
+            dF = np.diff(np.array(Fh), axis=0).T
+            dG = np.diff(np.array(Gh), axis=0).T
+            gam, *_ = np.linalg.lstsq(dF, f.ravel(), rcond=None)
+            x = (gx.ravel() - dG @ gam).reshape(gx.shape)
+        return gx, max_iter, False
+
+    def time_integrals(self, c: int, q: np.ndarray, dt: float, mu: float):
+        """qbar, volume term and face traces from the converged predictor (R4).
+
+        Returns dict with
+            qbar   [ndof, 5]          dt sum_a w_a q[a]
+            vol    [ndof, 5]          sum_k P_k^T |J_k| sum_d V^_d F*bar_{d,k}
+            tq     [K, nf, 5]         qbar at each boundary triangle's nodes
+            tF     [K, nf, 3, 5]      dt sum_a w_a F(q[a]) there (sub-tet k's gradient)
+        """
+        g = self.grids[c]
+        w = self.tb.w
+        F = self._nodal_flux(c, q, mu)
+        fstar = self._contravariant(c, F, dt)
+        fbar = np.einsum("a,akpdv->kpdv", w, fstar)
+        vk = np.einsum("k,dpm,kmdv->kpv", g.detJ, self.ref.V_f, fbar)
+        vol = np.zeros((g.ndof, 5))
+        np.add.at(vol, g.conn, vk)
+        qbar = dt * np.einsum("a,anv->nv", w, q)
+        fn = self.ref.face_nodes_a
+        tq = qbar[g.face_dof]
+        tF = dt * np.einsum("a,akjxv->kjxv", w, F[:, :, fn])
+        return dict(qbar=qbar, vol=vol, tq=tq, tF=tF)
+
+    # --------------------------------------------------------------- corrector
+    def rusanov(self, c: int, k: int, ti: dict, mus: dict, dt: float) -> np.ndarray:
+        """Time-integrated Rusanov flux G [nf, 5] at the nodes of cell c's boundary
+        triangle k, eq. (3.33) with the readings R4-R5."""
+        g = self.grids[c]
+        gam = self.p.gamma
+        N = self.N
+        nb = int(g.nbr[k])
+        kn = int(g.nbr_tri[k])
+        perm = g.nbr_perm[k]
+        qi, Fi = ti[c]["tq"][k], ti[c]["tF"][k]
+        qo, Fo = ti[nb]["tq"][kn][perm], ti[nb]["tF"][kn][perm]
+        n = g.tri_normal[k]
+        wi, wo = qi / dt, qo / dt
+        vi = wi[:, 1:4] / wi[:, :1]
+        vo = wo[:, 1:4] / wo[:, :1]
+        lam = max(float((np.abs(vi @ n) + sound_speed(wi, gam)).max()),
+                  float((np.abs(vo @ n) + sound_speed(wo, gam)).max()))
+        lamv = max(float(visc_eig(wi, mus[c]).max()), float(visc_eig(wo, mus[nb]).max()))
+        eps = (2 * N + 1) / ((g.h + self.grids[nb].h) * math.sqrt(math.pi / 2.0))
+        s = lam + 2.0 * eps * lamv
+        return 0.5 * np.einsum("jxv,x->jv", Fo + Fi, n) - 0.5 * s * (qo - qi)
+
+    def face_term(self, c: int, ti: dict, mus: dict, dt: float) -> np.ndarray:
+        """sum_t P_t^T 2 A_t Z^ G_t (R5)."""
+        g = self.grids[c]
+        out = np.zeros((g.ndof, 5))
+        for k in range(len(g.conn)):
+            Gf = self.rusanov(c, k, ti, mus, dt)
+            np.add.at(out, g.face_dof[k], 2.0 * g.tri_area[k] * (self.ref.Z_f @ Gf))
+        return out
+
+    # -------------------------------------------------------------------- step
+    def ring(self) -> list:
+        """Target cells and their face neighbours."""
+        ring = set(self.targets)
+        for c in self.targets:
+            ring.update(int(x) for x in self.grids[c].nbr)
+        return sorted(ring)
+
+    def step(self, u: np.ndarray, dt: float, depth=None, tol=None, max_iter=None, keep=False):
+        """One ADER step: detector, predictor, corrector, positivity check.
+        Returns (u_new, report); only target cells of u_new are updated.
+        keep=True also stores the predictor results in report.pred / report.ti."""
+        rep = StepReport()
+        ring = self.ring()
+        mus = {}
+        for c in ring:
+            if self.p.av:
+                beta, mu_c = self.detector(u, c)
+            else:
+                beta, mu_c = 0.0, self.p.mu
+            mus[c] = mu_c
+            rep.beta[c] = beta
+        rep.mu = mus
+        ti = {}
+        for c in ring:
+            un = self.cell_state(u, c)
+            q, it, ok = self.predictor(c, un, dt, mus[c], depth, tol, max_iter)
+            rep.iters[c] = it
+            rep.converged &= ok
+            ti[c] = self.time_integrals(c, q, dt, mus[c])
+            if keep:
+                rep.pred[c] = q
+        if keep:
+            rep.ti = ti
+        unew = u.copy()
+        for c in self.targets:
+            rhs = ti[c]["vol"] - self.face_term(c, ti, mus, dt)
+            du = self.mass_solve(c, rhs)
+            newc = self.cell_state(u, c) + du
+            unew[:, self.dof_ptr[c]:self.dof_ptr[c + 1]] = newc.T
+            ok = bool(np.all(np.isfinite(newc)) and np.all(newc[:, 0] > 0) and np.all(pressure(newc, self.p.gamma) > 0))
+            rep.positive &= ok
+        return unew, rep
+
+    # ----------------------------------------------------------------- metrics
+    def l2_error(self, u: np.ndarray, exact_fn, var: int = 0, qorder_pts=None) -> float:
+        """(sum_cells int |rho_h - rho_e|^2)^(1/2) over target cells, each sub-tet
+        integrated with a Grundmann-Moeller rule of degree 2N+3."""
+        from .quadrature import tet_rule
+        pts, wts = tet_rule(2 * self.N + 3)
+        phi = self.ref.eval_basis(pts)
+        L = self.mesh["box"]
+        tot = 0.0
+        for c in self.targets:
+            g = self.grids[c]
+            uc = self.cell_state(u, c)[:, var]
+            for k in range(len(g.conn)):
+                x = g.X[k, 0] + pts @ g.J[k].T
+                uh = phi @ uc[g.conn[k]]
+                ue = exact_fn(np.mod(x, L))
+                tot += g.detJ[k] * float(wts @ (uh - ue) ** 2)
+        return math.sqrt(tot)
