@@ -1,0 +1,185 @@
+/*
+ * afe.h -- C ABI of libafe: the ADER-AFE-DG hot path on one AMD Instinct GPU.
+ *
+ * The method (Michel, Diazzi, Boscheri: "Continuous 3D finite element subgrid
+ * basis functions for discontinuous Galerkin methods on polyhedral meshes"):
+ * each polyhedral cell P_i carries continuous P_N Lagrange functions on a
+ * sub-tetrahedral grid (Sec. 4.1, eq:interp_u); one time step is a cell-local
+ * space-time Galerkin predictor (Sec. 4.3, eq:ADER-localCauchy, eq:ader4)
+ * followed by a quadrature-free corrector with Rusanov face fluxes (Sec. 4.4)
+ * and a flattener-driven artificial viscosity (Sec. 4.5); the time step obeys
+ * eqn.timestep (Sec. 4.2).
+ *
+ * Conventions for every call:
+ *   - Pointers are host pointers unless the argument says "device".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it; calls that return host values synchronise it.
+ *   - Errors are reported by the returned afe_status; nothing is thrown across
+ *     the ABI.  afe_last_error() gives a message for the calling thread.
+ *   - The state u is caller-owned device memory, FP64, SoA u[5][ndof] with the
+ *     conserved variables (rho, rho u, rho v, rho w, rho E) and the DOFs in
+ *     cell-major order (cell c owns [cell_dof_ptr[c], cell_dof_ptr[c+1]) ).
+ *   - Everything reached from an afe_cell_data is owned by the library and
+ *     released by afe_free.  A cell-data object may be used from one host
+ *     thread at a time; calls on one object on different streams race.
+ */
+#ifndef AFE_H
+#define AFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AFE_OK = 0,
+    AFE_E_ARG = -1,               /* invalid argument                               */
+    AFE_E_BAD_MESH = -2,          /* open cell, unmatched face, vertex seen twice   */
+    AFE_E_DEGENERATE_SUBTET = -3, /* a sub-tetrahedron with |det J| <= 0            */
+    AFE_E_NO_CONVERGENCE = -4,    /* predictor did not reach tol within max_iter    */
+    AFE_E_POSITIVITY = -5,        /* rho <= 0 or p <= 0 at a DOF after the update   */
+    AFE_E_HBM_BUDGET = -6,        /* device memory needed exceeds params.hbm_budget */
+    AFE_E_HIP = -7,               /* a HIP runtime call failed                      */
+    AFE_E_NONFINITE = -8          /* NaN or Inf in the state after the update       */
+} afe_status;
+
+/* Polyhedral mesh of a periodic cube [0, box)^3 (host arrays, copied).
+ * Each vertex is stored once; a face is a polygon listed once, oriented outward
+ * from its owner by the right-hand rule; a corner's position in the owner's
+ * frame is xyz[v] + face_vshift[corner] * box, and the neighbour's seed in the
+ * owner's frame is shifted by nbr_shift * box, so the neighbour sees the
+ * corner at xyz[v] + (face_vshift - nbr_shift) * box. */
+typedef struct {
+    int32_t n_vertices;
+    const double *xyz;          /* [n_vertices][3]                              */
+    int32_t n_faces;
+    const int32_t *face_ptr;    /* [n_faces + 1] CSR offsets into face_vtx      */
+    const int32_t *face_vtx;    /* [face_ptr[n_faces]] corner vertex ids         */
+    const int8_t *face_vshift;  /* [face_ptr[n_faces]][3] corner image shifts    */
+    const int32_t *face_cell;   /* [n_faces][2] owner, neighbour                 */
+    const int8_t *nbr_shift;    /* [n_faces][3] neighbour image shift            */
+    int32_t n_cells;
+    double box;                 /* edge of the periodic cube                    */
+} afe_mesh;
+
+enum { AFE_FP64 = 0, AFE_MIXED = 1 };
+
+/* Physics and solver parameters (Sec. 2, Sec. 4.3, Sec. 4.5). */
+typedef struct {
+    double gamma;        /* ratio of specific heats (1.4 in the paper)              */
+    double mu;           /* physical dynamic viscosity (0 = Euler)                  */
+    double m1;           /* flattener constant m1 (0.1, Sec. 4.5)                   */
+    int32_t av;          /* 1: artificial viscosity from the flattener              */
+    int32_t max_iter;    /* predictor iteration cap                                 */
+    double tol;          /* predictor stop: max|G(q)-q| <= tol * max(1, max|G(q)|)  */
+    int32_t accel_depth; /* Anderson depth m of the predictor iteration (0 = plain)  */
+    int32_t precision;   /* AFE_FP64 (AFE_MIXED is rejected by this version)        */
+    size_t hbm_budget;   /* bytes of device memory the object may use (0 = no cap)  */
+} afe_params;
+
+typedef struct {
+    int64_t ndof;          /* total cell DOFs (per conserved variable)  */
+    int32_t n_cells;
+    int64_t n_subtets;
+    int32_t N;             /* polynomial degree                         */
+    int32_t max_cell_dofs; /* largest N_i                               */
+    int32_t max_cell_subtets;
+    size_t device_bytes;   /* device memory held by the object          */
+    double h_min;          /* smallest cell diameter                    */
+} afe_info;
+
+typedef struct {
+    int32_t iters_min, iters_max; /* predictor iterations over cells           */
+    double iters_mean;
+    int32_t n_troubled;           /* cells with flattener beta > 0             */
+    int32_t status_cell;          /* first failing cell, -1 if none            */
+} afe_step_report;
+
+typedef struct afe_cell_data afe_cell_data;
+
+/* Build the sub-tetrahedral grid and all per-cell data of `mesh` for degree N
+ * (Sec. 4.1): every polygon is fanned about its vertex-mean centroid and coned
+ * to the cell's vertex-mean centroid; the cell DOFs are the sub-tet nodes
+ * without repetition; sub-tet Jacobians, boundary sub-triangles and their
+ * pairing with the neighbour's, and the inverse cell mass matrices M_i^{-1}
+ * (Sec. 4.4, M_i; Sec. 4.3, the stored inverse of K_1,i) are computed.
+ * 1 <= N <= 3.  On success *out owns all device memory of the object.
+ * Errors: AFE_E_ARG, AFE_E_BAD_MESH, AFE_E_DEGENERATE_SUBTET,
+ * AFE_E_HBM_BUDGET, AFE_E_HIP. */
+afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params *params,
+                               void *stream, afe_cell_data **out);
+
+/* Sizes of a built object. */
+afe_status afe_query(const afe_cell_data *cd, afe_info *out);
+
+/* Cell DOF offsets: cell_dof_ptr [n_cells + 1] (host, int64). */
+afe_status afe_cell_dof_ptr(const afe_cell_data *cd, int64_t *cell_dof_ptr);
+
+/* DOF coordinates in each cell's frame: xyz device [3][ndof]. */
+afe_status afe_dof_coords(const afe_cell_data *cd, double *xyz, void *stream);
+
+/* Sub-grid connectivity for inspection (host copies):
+ *   subtet_ptr [n_cells + 1] int64, conn [n_subtets][np] int32 cell-local DOF of
+ *   each sub-tet node (np = (N+1)(N+2)(N+3)/6, App. A node order),
+ *   nbr_subtet [n_subtets] int32 global index of the neighbour's sub-tet on the
+ *   same boundary triangle, nbr_perm [n_subtets][nf] int32 matching face node.
+ * Any output pointer may be NULL. */
+afe_status afe_connectivity(const afe_cell_data *cd, int64_t *subtet_ptr, int32_t *conn,
+                            int32_t *nbr_subtet, int32_t *nbr_perm);
+
+/* Host-only construction of the same sub-grid (no device memory, no GPU):
+ * afe_subgrid_sizes returns sizes[0] = number of sub-tets, sizes[1] = number
+ * of DOFs; afe_subgrid_host fills caller-allocated host arrays:
+ *   subtet_ptr, dof_ptr [n_cells + 1] int64; conn [nsub][np] int32;
+ *   nbr_subtet [nsub] int32; nbr_perm [nsub][nf] int32;
+ *   geo [nsub][10] (J^{-1} row-major, |det J|); tri [nsub][4] (2 * area of the
+ *   boundary triangle, unit outward normal).  Any output may be NULL.
+ * Errors as for build_afe_cell_data (no AFE_E_HIP). */
+afe_status afe_subgrid_sizes(const afe_mesh *mesh, int32_t N, int64_t *sizes);
+afe_status afe_subgrid_host(const afe_mesh *mesh, int32_t N, int64_t *subtet_ptr, int64_t *dof_ptr,
+                            int32_t *conn, int32_t *nbr_subtet, int32_t *nbr_perm, double *geo, double *tri);
+
+/* Convert primitive (rho, u, v, w, p) to conserved variables (Sec. 2, EOS):
+ * prim and u are device [5][ndof]; they may alias. */
+afe_status afe_prim_to_cons(afe_cell_data *cd, const double *prim, double *u, void *stream);
+
+/* Time step of eqn.timestep for state u (device): runs the detector of
+ * Sec. 4.5 (for mu_i) and returns dt = cfl * h_min / ((2N+1) max(|lambda| +
+ * 2 |lambda^v| (2N+1)/h_i)) in *dt_host.  Synchronises `stream`. */
+afe_status ader_cfl_dt(afe_cell_data *cd, const double *u, double cfl, double *dt_host, void *stream);
+
+/* Detector + space-time predictor of Sec. 4.3 for every cell from state u
+ * (device), time step dt.  Leaves in library buffers the time-integrated
+ * volume term and the face traces used by ader_correct.  Non-convergence is
+ * latched in the object's device status word (reported by ader_step). */
+afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *stream);
+
+/* Corrector of Sec. 4.4 after ader_predict on the same u and dt: Rusanov
+ * fluxes on all boundary sub-triangles, u <- u + M_i^{-1}(volume - faces)
+ * in place, then the positivity check (latched in the status word). */
+afe_status ader_correct(afe_cell_data *cd, double *u, double dt, void *stream);
+
+/* One full ADER step u^n -> u^{n+1} in place (device u): predict + correct,
+ * then one synchronisation to read the status word.  Fills *rep when not NULL.
+ * Returns AFE_E_NO_CONVERGENCE, AFE_E_POSITIVITY or AFE_E_NONFINITE when the
+ * step failed (u then holds the failed update). */
+afe_status ader_step(afe_cell_data *cd, double *u, double dt, afe_step_report *rep, void *stream);
+
+/* Copy the last predictor solution (the space-time nodal values q of
+ * eq:ader4) to device memory q [ndof][(N+1)*5]: DOF-major, then time node,
+ * then conserved variable. */
+afe_status afe_predictor_state(const afe_cell_data *cd, double *q, void *stream);
+
+/* Per-cell predictor iteration counts and viscosities of the last step
+ * (host arrays [n_cells]); either may be NULL.  Synchronises `stream`. */
+afe_status afe_cell_diagnostics(const afe_cell_data *cd, int32_t *iters, double *mu, void *stream);
+
+void afe_free(afe_cell_data *cd);
+const char *afe_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFE_H */

@@ -1,0 +1,88 @@
+// Device-side layout of an afe_cell_data object and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace afe {
+
+// Reference data in device memory (one copy per object).
+struct DevRef {
+    double M[20 * 20];       // M^[m][p] = int phi_m phi_p
+    double K[3 * 20 * 20];   // K^_d[m][p] = int phi_m d_d phi_p
+    double D[3 * 20 * 20];   // D^_d[m][p] = d_d phi_p (x_m)
+    double Z[10 * 10];       // face mass on the reference triangle
+    double zsum[10];         // int_tri phi_j = sum_i Z[i][j]
+    double w[4];             // Gauss-Legendre weights on [0, 1]
+    double Ktau_inv[16];     // inverse of the upwind time operator
+    int fn[10];              // face node -> reference node
+};
+
+struct DevGrid {
+    int N, np, nf, nt, nc;   // nc = 5 * nt columns of the space-time blocks
+    int n_cells;
+    int64_t ndof, nsub;
+    int max_cell_dofs;
+    double gamma, mu, m1;
+    int av;
+    // connectivity and geometry
+    const int64_t *dof_ptr;   // [n_cells + 1]
+    const int64_t *sub_ptr;   // [n_cells + 1]
+    const int64_t *minv_ptr;  // [n_cells + 1] offsets of the dense M_i^{-1}
+    const int32_t *conn;      // [nsub][np]
+    const int32_t *sub_cell;  // [nsub]
+    const double *geo;        // [nsub][10]
+    const double *tri;        // [nsub][4]
+    const int32_t *nbr_sub;   // [nsub]
+    const int32_t *perm;      // [nsub][nf]
+    const double *h, *vol;    // [n_cells]
+    const double *mrow;       // [ndof]
+    const int32_t *dof_cell;  // [ndof]
+    const int32_t *inc_ptr, *inc_idx;
+    const int32_t *finc_ptr, *finc_idx;
+    const DevRef *ref;
+    double *minv;             // dense M_i^{-1}, row-major, symmetric
+};
+
+// Work buffers of the predictor / corrector.
+struct DevWork {
+    double *x;       // [ndof][nc] current predictor iterate (final: the solution)
+    double *R;       // [ndof][nc] assembled stiffness term
+    double *S;       // [ndof][nc] M^{-1} R
+    double *rk;      // [nsub][np][nc] per-sub-tet contributions
+    double *fprev;   // [ndof][nc]
+    double *gprev;   // [ndof][nc]
+    double *fcur;    // [ndof][nc]
+    double *gcur;    // [ndof][nc]
+    double *dF;      // per cell: depth columns of n_c * nc (append-only)
+    double *dG;
+    double *gram;    // [n_cells][63][63] Cholesky rows, then [n_cells][63] column scales
+    int32_t *hist;   // [n_cells][2]: stored difference pairs
+    double *trace;   // [nsub][nf][20]: qbar (5), Fbar (15) at face nodes
+    double *vk;      // [nsub][np][5] volume-term contributions
+    double *fc;      // [nsub][nf][5] face-term contributions
+    double *rhs;     // [ndof][5]
+    double *mu_cell; // [n_cells]
+    double *beta;    // [n_cells]
+    double *cflterm; // [n_cells]
+    int32_t *active; // [n_cells]
+    int32_t *iters;  // [n_cells]
+    int32_t *status; // [4]: flags, first bad cell, active count, troubled count
+    int depth;
+};
+
+enum : int { kStatusNoConv = 1, kStatusPositivity = 2, kStatusNonfinite = 4 };
+
+hipError_t launch_reset_status(const DevGrid &g, const DevWork &w, hipStream_t s);
+hipError_t launch_mass_assemble(const DevGrid &g, hipStream_t s);
+hipError_t launch_mass_invert(const DevGrid &g, hipStream_t s);
+hipError_t launch_prim_to_cons(const DevGrid &g, const double *prim, double *u, hipStream_t s);
+hipError_t launch_detect(const DevGrid &g, const DevWork &w, const double *u, hipStream_t s);
+hipError_t launch_cfl_max(const DevGrid &g, const DevWork &w, double *out, hipStream_t s);
+hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, const double *u, hipStream_t s);
+hipError_t launch_pred_iteration(const DevGrid &g, const DevWork &w, const double *u, double dt, int it,
+                                 int max_iter, double tol, hipStream_t s);
+hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, double dt, hipStream_t s);
+hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, double dt, hipStream_t s);
+
+}  // namespace afe

@@ -1,0 +1,33 @@
+// Reference tetrahedron data for the P_N AFE basis and the Gauss-Legendre
+// time basis (host side, computed once per degree).
+#pragma once
+#include <array>
+#include <vector>
+
+namespace afe {
+
+constexpr int kMaxN = 3;
+constexpr int kMaxNp = 20;  // (N+1)(N+2)(N+3)/6 at N = 3
+constexpr int kMaxNf = 10;  // (N+1)(N+2)/2 at N = 3
+constexpr int kMaxNt = 4;   // N + 1 time nodes
+
+struct RefData {
+    int N = 0, np = 0, nf = 0, nt = 0;
+    // node lattice: integer barycentric weights N*(lambda1..lambda4) per node,
+    // lambda1 = 1 - r - s - t, lambda2 = r, lambda3 = s, lambda4 = t
+    std::vector<std::array<int, 4>> bary;
+    std::vector<std::array<double, 3>> xi;  // reference coordinates (r, s, t)
+    std::vector<int> face_nodes;            // nodes with t = 0, in node order
+    std::vector<double> M;                  // [np][np]   int phi_m phi_l
+    std::vector<double> K;                  // [3][np][np] int phi_m d_d phi_l
+    std::vector<double> D;                  // [3][np][np] d_d phi_l (x_m)
+    std::vector<double> Z;                  // [nf][nf]  face mass, reference triangle
+    // time basis on [0, 1]
+    std::vector<double> tau, w;             // Gauss-Legendre nodes and weights
+    std::vector<double> Ktau, Ktau_inv;     // [nt][nt]
+};
+
+// Builds the exact reference data for 1 <= N <= 3 (cached).
+const RefData &ref_data(int N);
+
+}  // namespace afe
