@@ -136,6 +136,7 @@ def build_cell(mesh: dict, c: int, N: int, cell_faces=None) -> CellGrid:
     g.keys = uniq
     g.dof_of = dof_of
     g.conn = np.array([[dof_of[k] for k in row] for row in node_keys], dtype=np.int64)
+    g.face_dof = g.conn[:, R.face_nodes_a]
     g.X = np.stack([X for _, X, _ in subtets])
     g.sub_ids = [ids for ids, _, _ in subtets]
     g.sub_face = np.array([f for _, _, f in subtets], dtype=np.int64)
@@ -185,7 +186,6 @@ def build_cells(mesh: dict, N: int, cells=None) -> dict[int, CellGrid]:
         g.nbr = np.zeros(K, dtype=np.int64)
         g.nbr_tri = np.zeros(K, dtype=np.int64)
         g.nbr_perm = np.zeros((K, len(fn)), dtype=np.int64)
-        g.face_dof = g.conn[:, fn]
         g.nbr_face_dof = np.zeros((K, len(fn)), dtype=np.int64)
         for k in range(K):
             f = int(g.sub_face[k])
@@ -224,12 +224,14 @@ def build_cells(mesh: dict, N: int, cells=None) -> dict[int, CellGrid]:
 
 
 def polyhedron_volume(g: CellGrid) -> float:
-    """Volume of the polyhedron from its faces by the divergence theorem,
-    |P| = 1/3 sum_f x_f . A_f, with A_f the vector area of polygon f
-    (1/2 sum of corner cross products) and x_f its first corner."""
+    """Volume enclosed by the cell's boundary surface by the divergence theorem:
+    each polygon (possibly non-planar) is the fan of triangles (a, b, F) about
+    its vertex-mean centroid F, and |P| = 1/6 sum det[a, b, F] over all fan
+    triangles (signed tetrahedra with the origin)."""
     tot = 0.0
     for _, pos in g.faces:
         k = len(pos)
-        A = 0.5 * sum(np.cross(pos[e], pos[(e + 1) % k]) for e in range(k))
-        tot += float(np.dot(pos[0], A)) / 3.0
+        F = pos.mean(axis=0)
+        for e in range(k):
+            tot += float(np.linalg.det(np.array([pos[e], pos[(e + 1) % k], F]))) / 6.0
     return tot
