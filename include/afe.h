@@ -176,6 +176,15 @@ afe_status afe_predictor_state(const afe_cell_data *cd, double *q, void *stream)
  * (host arrays [n_cells]); either may be NULL.  Synchronises `stream`. */
 afe_status afe_cell_diagnostics(const afe_cell_data *cd, int32_t *iters, double *mu, void *stream);
 
+/* Timing of the dominant kernel (the M_i^{-1} application of the predictor
+ * iteration, Sec. 4.3 eq:ader4): when enabled, HIP events bracket each of its
+ * launches on the object's stream and the kernel counts the algorithmic bytes
+ * it moves (8 N_i^2 of M_i^{-1} plus the space-time blocks read and written,
+ * 16 N_i 5(N+1), per cell and iteration).  afe_profile_read returns the sums
+ * since the last enable. */
+afe_status afe_profile_enable(afe_cell_data *cd, int32_t enable);
+afe_status afe_profile_read(afe_cell_data *cd, double *kernel_ms, int64_t *launches, double *bytes);
+
 void afe_free(afe_cell_data *cd);
 const char *afe_last_error(void);
 

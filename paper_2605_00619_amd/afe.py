@@ -28,7 +28,7 @@ EXPORTED = [
     "build_afe_cell_data", "afe_query", "afe_cell_dof_ptr", "afe_dof_coords", "afe_connectivity",
     "afe_prim_to_cons", "ader_cfl_dt", "ader_predict", "ader_correct", "ader_step",
     "afe_predictor_state", "afe_cell_diagnostics", "afe_free", "afe_last_error", "afe_subgrid_sizes",
-    "afe_subgrid_host",
+    "afe_subgrid_host", "afe_profile_enable", "afe_profile_read",
 ]
 
 
@@ -100,6 +100,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afe_subgrid_sizes": ([ctypes.POINTER(_Mesh), i32, vp], i32),
         "afe_subgrid_host": ([ctypes.POINTER(_Mesh), i32, vp, vp, vp, vp, vp, vp, vp], i32),
         "afe_last_error": ([], ctypes.c_char_p),
+        "afe_profile_enable": ([vp, i32], i32),
+        "afe_profile_read": ([vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -274,6 +276,17 @@ class CellData:
         q = torch.empty((self.ndof, 5 * (self.N + 1)), dtype=torch.float64, device="cuda")
         _check(_lib.afe_predictor_state(self._h, _dev(q), _stream(stream)))
         return q
+
+    def profile_enable(self, on: bool = True) -> None:
+        _check(_lib.afe_profile_enable(self._h, int(on)))
+
+    def profile_read(self):
+        """(milliseconds, launches, algorithmic bytes) of the predictor's M^-1 kernel."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        b = ctypes.c_double()
+        _check(_lib.afe_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return float(ms.value), int(n.value), float(b.value)
 
     def diagnostics(self, stream=None):
         it = np.zeros(self.n_cells, dtype=np.int32)

@@ -42,6 +42,12 @@ struct afe_cell_data {
     double *d_scalar = nullptr;  // device scratch scalar (CFL max)
     int32_t *h_status = nullptr; // pinned host copy of the status word
     double *h_scalar = nullptr;
+    // profiling of the predictor's M^{-1} kernel
+    bool prof_on = false;
+    afe::ProfileHooks hooks{};
+    unsigned long long *h_bytes = nullptr;
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0;
 
     template <typename T>
     hipError_t alloc(T *&p, size_t count) {
@@ -65,6 +71,9 @@ struct afe_cell_data {
         return e;
     }
     ~afe_cell_data() {
+        if (hooks.start) (void)hipEventDestroy(hooks.start);
+        if (hooks.stop) (void)hipEventDestroy(hooks.stop);
+        if (h_bytes) (void)hipHostFree(h_bytes);
         for (void *p : allocs) (void)hipFree(p);
         if (h_status) (void)hipHostFree(h_status);
         if (h_scalar) (void)hipHostFree(h_scalar);
@@ -80,12 +89,13 @@ size_t estimate_bytes(const afe::HostGrid &h, int depth) {
         size_t n = size_t(h.dof_ptr[c + 1] - h.dof_ptr[c]);
         b += n * n * sizeof(double);
     }
-    b += size_t(h.ndof) * nc * sizeof(double) * (7 + 2 * size_t(std::max(depth, 1)));
+    b += size_t(h.ndof) * nc * sizeof(double) * (5 + 2 * size_t(std::max(depth, 1)));
+    b += size_t(h.n_cells) * ((h.max_cell_dofs + 63) / 64) * 130 * sizeof(double);
     b += size_t(h.nsub) * h.np * nc * sizeof(double);
     b += size_t(h.nsub) * h.nf * 25 * sizeof(double) + size_t(h.nsub) * h.np * 5 * sizeof(double);
     b += size_t(h.ndof) * (5 * 8 + 3 * 8 + 8 + 4 + 8);
     b += size_t(h.nsub) * (h.np * 4 + 10 * 8 + 4 * 8 + 4 + 4 + h.nf * 4);
-    b += size_t(h.n_cells) * (63 * 64 * 8 + 64);
+    b += size_t(h.n_cells) * ((2 * 63 * 63 + 63) * 8 + 64);
     return b;
 }
 
@@ -135,6 +145,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     g.ndof = h.ndof;
     g.nsub = h.nsub;
     g.max_cell_dofs = h.max_cell_dofs;
+    g.max_cell_subtets = h.max_cell_subtets;
     g.gamma = params->gamma;
     g.mu = params->mu;
     g.m1 = params->m1;
@@ -197,11 +208,13 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     if ((e = cd->alloc(g.minv, size_t(minv_ptr[h.n_cells]))) != hipSuccess ||
         (e = cd->alloc(w.x, nd * nc)) != hipSuccess || (e = cd->alloc(w.R, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.S, nd * nc)) != hipSuccess || (e = cd->alloc(w.fprev, nd * nc)) != hipSuccess ||
-        (e = cd->alloc(w.gprev, nd * nc)) != hipSuccess || (e = cd->alloc(w.fcur, nd * nc)) != hipSuccess ||
-        (e = cd->alloc(w.gcur, nd * nc)) != hipSuccess ||
+        (e = cd->alloc(w.gprev, nd * nc)) != hipSuccess || 
+        (e = cd->alloc(w.part, size_t(h.n_cells) * ((h.max_cell_dofs + 63) / 64) * 130)) != hipSuccess ||
+        (e = cd->alloc(w.gamma, size_t(h.n_cells) * 63)) != hipSuccess ||
+        (e = cd->alloc(w.kuse, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.dF, nd * nc * dslots)) != hipSuccess ||
         (e = cd->alloc(w.dG, nd * nc * dslots)) != hipSuccess ||
-        (e = cd->alloc(w.gram, size_t(h.n_cells) * 63 * 64)) != hipSuccess ||
+        (e = cd->alloc(w.gram, size_t(h.n_cells) * (2 * 63 * 63 + 63))) != hipSuccess ||
         (e = cd->alloc(w.hist, size_t(h.n_cells) * 2)) != hipSuccess ||
         (e = cd->alloc(w.rk, size_t(h.nsub) * h.np * nc)) != hipSuccess ||
         (e = cd->alloc(w.trace, size_t(h.nsub) * h.nf * 20)) != hipSuccess ||
@@ -211,7 +224,8 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(w.mu_cell, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.beta, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.cflterm, size_t(h.n_cells))) != hipSuccess ||
-        (e = cd->alloc(w.active, size_t(h.n_cells))) != hipSuccess ||
+        (e = cd->alloc(w.alist, size_t(h.n_cells) * 2)) != hipSuccess ||
+        (e = cd->alloc(w.acount, 2)) != hipSuccess ||
         (e = cd->alloc(w.iters, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.status, 4)) != hipSuccess || (e = cd->alloc(cd->d_scalar, 1)) != hipSuccess ||
         (e = hipHostMalloc(&cd->h_status, 4 * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
@@ -325,11 +339,22 @@ afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *str
     HIP_TRY(afe::launch_reset_status(cd->g, cd->w, s));
     HIP_TRY(afe::launch_detect(cd->g, cd->w, u, s));
     HIP_TRY(afe::launch_pred_init(cd->g, cd->w, u, s));
-    for (int it = 0; it < p.max_iter; ++it) {
-        HIP_TRY(afe::launch_pred_iteration(cd->g, cd->w, u, dt, it, p.max_iter, p.tol, s));
-        HIP_TRY(hipMemcpyAsync(cd->h_status, cd->w.status, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int n_list = cd->host.n_cells;
+    for (int it = 0; it < p.max_iter && n_list > 0; ++it) {
+        const int cur = it % 2, nxt = 1 - cur;
+        int32_t *list = cd->w.alist + size_t(cur) * cd->host.n_cells;
+        int32_t *next = cd->w.alist + size_t(nxt) * cd->host.n_cells;
+        HIP_TRY(afe::launch_pred_iteration(cd->g, cd->w, u, dt, it, p.max_iter, p.tol, list, n_list, next,
+                                           cd->w.acount + nxt, s, cd->prof_on ? &cd->hooks : nullptr));
+        HIP_TRY(hipMemcpyAsync(cd->h_status + 2, cd->w.acount + nxt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        if (cd->h_status[2] <= 0) break;
+        n_list = cd->h_status[2];
+        if (cd->prof_on) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventElapsedTime(&ms, cd->hooks.start, cd->hooks.stop));
+            cd->prof_ms += ms;
+            cd->prof_launches += 1;
+        }
     }
     HIP_TRY(afe::launch_pred_post(cd->g, cd->w, dt, s));
     return AFE_OK;
@@ -369,6 +394,30 @@ afe_status ader_step(afe_cell_data *cd, double *u, double dt, afe_step_report *r
     if (flags & afe::kStatusNonfinite) return fail(AFE_E_NONFINITE, "non-finite state after the update");
     if (flags & afe::kStatusNoConv) return fail(AFE_E_NO_CONVERGENCE, "predictor did not converge");
     if (flags & afe::kStatusPositivity) return fail(AFE_E_POSITIVITY, "density or pressure not positive");
+    return AFE_OK;
+}
+
+afe_status afe_profile_enable(afe_cell_data *cd, int32_t enable) {
+    if (!cd) return fail(AFE_E_ARG, "null argument");
+    if (enable && !cd->hooks.start) {
+        HIP_TRY(hipEventCreate(&cd->hooks.start));
+        HIP_TRY(hipEventCreate(&cd->hooks.stop));
+        HIP_TRY(cd->alloc(cd->hooks.bytes, 1));
+    }
+    cd->prof_on = enable != 0;
+    cd->prof_ms = 0.0;
+    cd->prof_launches = 0;
+    if (cd->hooks.bytes) HIP_TRY(hipMemset(cd->hooks.bytes, 0, sizeof(unsigned long long)));
+    return AFE_OK;
+}
+
+afe_status afe_profile_read(afe_cell_data *cd, double *kernel_ms, int64_t *launches, double *bytes) {
+    if (!cd) return fail(AFE_E_ARG, "null argument");
+    unsigned long long b = 0;
+    if (cd->hooks.bytes) HIP_TRY(hipMemcpy(&b, cd->hooks.bytes, sizeof(b), hipMemcpyDeviceToHost));
+    if (kernel_ms) *kernel_ms = cd->prof_ms;
+    if (launches) *launches = cd->prof_launches;
+    if (bytes) *bytes = double(b);
     return AFE_OK;
 }
 

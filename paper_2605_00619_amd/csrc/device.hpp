@@ -22,7 +22,7 @@ struct DevGrid {
     int N, np, nf, nt, nc;   // nc = 5 * nt columns of the space-time blocks
     int n_cells;
     int64_t ndof, nsub;
-    int max_cell_dofs;
+    int max_cell_dofs, max_cell_subtets;
     double gamma, mu, m1;
     int av;
     // connectivity and geometry
@@ -50,13 +50,14 @@ struct DevWork {
     double *R;       // [ndof][nc] assembled stiffness term
     double *S;       // [ndof][nc] M^{-1} R
     double *rk;      // [nsub][np][nc] per-sub-tet contributions
-    double *fprev;   // [ndof][nc]
-    double *gprev;   // [ndof][nc]
-    double *fcur;    // [ndof][nc]
-    double *gcur;    // [ndof][nc]
+    double *fprev;   // [ndof][nc] residual G(x) - x of the current iterate
+    double *gprev;   // [ndof][nc] G(x) of the current iterate
+    double *part;    // [n_cells][tiles of 64 DOFs][2 * 64 + 2] partial dots and norms
+    double *gamma;   // [n_cells][63] Anderson coefficients
+    int32_t *kuse;   // [n_cells] history columns used by the update
     double *dF;      // per cell: depth columns of n_c * nc (append-only)
     double *dG;
-    double *gram;    // [n_cells][63][63] Cholesky rows, then [n_cells][63] column scales
+    double *gram;    // [n_cells][63][63] Cholesky rows, [n_cells][63][63] Gram, [n_cells][63] scales
     int32_t *hist;   // [n_cells][2]: stored difference pairs
     double *trace;   // [nsub][nf][20]: qbar (5), Fbar (15) at face nodes
     double *vk;      // [nsub][np][5] volume-term contributions
@@ -65,13 +66,20 @@ struct DevWork {
     double *mu_cell; // [n_cells]
     double *beta;    // [n_cells]
     double *cflterm; // [n_cells]
-    int32_t *active; // [n_cells]
+    int32_t *alist;  // [2][n_cells] lists of cells still iterating (ping-pong)
+    int32_t *acount; // [2] their lengths
     int32_t *iters;  // [n_cells]
     int32_t *status; // [4]: flags, first bad cell, active count, troubled count
     int depth;
 };
 
 enum : int { kStatusNoConv = 1, kStatusPositivity = 2, kStatusNonfinite = 4 };
+
+// Events bracketing one launch of the predictor's M^{-1} kernel and its byte counter.
+struct ProfileHooks {
+    hipEvent_t start, stop;
+    unsigned long long *bytes;
+};
 
 hipError_t launch_reset_status(const DevGrid &g, const DevWork &w, hipStream_t s);
 hipError_t launch_mass_assemble(const DevGrid &g, hipStream_t s);
@@ -81,7 +89,8 @@ hipError_t launch_detect(const DevGrid &g, const DevWork &w, const double *u, hi
 hipError_t launch_cfl_max(const DevGrid &g, const DevWork &w, double *out, hipStream_t s);
 hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, const double *u, hipStream_t s);
 hipError_t launch_pred_iteration(const DevGrid &g, const DevWork &w, const double *u, double dt, int it,
-                                 int max_iter, double tol, hipStream_t s);
+                                 int max_iter, double tol, const int32_t *list, int n_list, int32_t *next,
+                                 int32_t *next_count, hipStream_t s, const ProfileHooks *prof);
 hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, double dt, hipStream_t s);
 hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, double dt, hipStream_t s);
 

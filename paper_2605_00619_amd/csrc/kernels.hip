@@ -247,11 +247,15 @@ __global__ void k_pred_init(DevGrid g, DevWork w, const double *__restrict__ u) 
         for (int a = 0; a < nt; ++a)
             for (int v = 0; v < 5; ++v) w.x[l * nc + a * 5 + v] = u[v * g.ndof + l];
     if (l < g.n_cells) {
-        w.active[l] = 1;
+        w.alist[l] = int32_t(l);
         w.iters[l] = 0;
         w.hist[2 * l] = 0;
         w.hist[2 * l + 1] = 0;
     }
+}
+
+__global__ void k_zero_int(int32_t *p) {
+    if (threadIdx.x == 0) p[0] = 0;
 }
 
 // Per sub-tet and time node: nodal flux, contravariant transform
@@ -261,7 +265,8 @@ __global__ void k_pred_init(DevGrid g, DevWork w, const double *__restrict__ u) 
 // the volume term |J| sum_d V^_d F*bar_d (Sec. 4.4) and the face traces
 // (qbar, Fbar) at the boundary-triangle nodes.
 template <int N, bool POST>
-__global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w, double dt) {
+__global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w, double dt,
+                                                             const int32_t *__restrict__ list, int chunks) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr int nf = Dim<N>::nf;
     __shared__ double Ks[3 * np * np];
@@ -276,12 +281,18 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
         Ds[t] = g.ref->D[t];
     }
     const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
-    const int64_t k = int64_t(blockIdx.x) * spb + s;
-    bool valid = (s < spb) && (k < g.nsub);
+    int64_t k;
+    bool valid;
     int c = 0;
-    if (valid) {
-        c = g.sub_cell[k];
-        if (!POST) valid = w.active[c] != 0;
+    if (POST) {
+        k = int64_t(blockIdx.x) * spb + s;
+        valid = (s < spb) && (k < g.nsub);
+        if (valid) c = g.sub_cell[k];
+    } else {
+        // block -> (active cell, chunk of spb of its sub-tets)
+        c = list[blockIdx.x / chunks];
+        k = g.sub_ptr[c] + int64_t(blockIdx.x % chunks) * spb + s;
+        valid = (s < spb) && (k < g.sub_ptr[c + 1]);
     }
     double G[9], dj = 0.0, mu_c = 0.0;
     double q[5] = {1, 0, 0, 0, 1};
@@ -370,275 +381,372 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
     }
 }
 
-// R[l][col] = sum over the DOF's incidence list of the sub-tet contributions.
+// R[l][col] = sum over the DOF's incidence list of the sub-tet contributions;
+// blocks cover the DOF-major blocks of the listed cells.
 template <int N>
-__global__ void __launch_bounds__(256) k_gather(DevGrid g, DevWork w) {
+__global__ void __launch_bounds__(256) k_gather(DevGrid g, DevWork w, const int32_t *__restrict__ list, int per) {
     constexpr int nc = Dim<N>::nc;
-    const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (t >= g.ndof * nc) return;
+    const int c = list[blockIdx.x / per];
+    const int64_t d0 = g.dof_ptr[c];
+    const int64_t e = int64_t(blockIdx.x % per) * blockDim.x + threadIdx.x;
+    if (e >= (g.dof_ptr[c + 1] - d0) * nc) return;
+    const int64_t t = d0 * nc + e;
     const int64_t l = t / nc;
     const int col = int(t % nc);
-    if (!w.active[g.dof_cell[l]]) return;
     double acc = 0.0;
-    for (int e = g.inc_ptr[l]; e < g.inc_ptr[l + 1]; ++e) acc += w.rk[int64_t(g.inc_idx[e]) * nc + col];
+    for (int q = g.inc_ptr[l]; q < g.inc_ptr[l + 1]; ++q) acc += w.rk[int64_t(g.inc_idx[q]) * nc + col];
     w.R[t] = acc;
 }
 
-// Y = M_i^{-1} X for every (active) cell, X and Y DOF-major with NC columns.
-// One wave owns up to 256 rows of one cell (4 groups of 64 rows, lane-strided);
-// M_i^{-1} is symmetric, so row j of the stored matrix supplies column j and
-// the loads of one j are coalesced across the wave.  X[j][:] is uniform over
-// the wave.  MODE 0: Y = S (predictor, active cells only);  MODE 1: add Y
-// into the SoA state u (corrector, all cells).
+// Y = M_i^{-1} X for the listed cells (list == nullptr: all cells), X and Y
+// DOF-major with NC columns.  A block of 4 waves owns 64 rows of one cell; the
+// waves split the inner index j into 4 contiguous ranges and their partial
+// sums are added in wave order through LDS (deterministic).  M_i^{-1} is
+// symmetric, so row j of the stored matrix supplies column j: one j is a
+// coalesced 512-byte load across the wave, and X[j][:] is wave-uniform.
+// MODE 0: Y = S (predictor);  MODE 1: add Y into the SoA state u (corrector).
 template <int NC, int MODE>
-__global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restrict__ active,
-                                               const double *__restrict__ X, double *__restrict__ Y, int tpc) {
+__global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restrict__ list,
+                                               const double *__restrict__ X, double *__restrict__ Y, int tpc,
+                                               unsigned long long *bytes) {
+    __shared__ double part[3][NC][kWave];
     const int lane = threadIdx.x % kWave;
-    const int64_t id = int64_t(blockIdx.x) * (blockDim.x / kWave) + threadIdx.x / kWave;
-    const int c = int(id / tpc);
-    const int tile = int(id % tpc);
-    if (c >= g.n_cells) return;
-    if (MODE == 0 && !active[c]) return;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int ci = blockIdx.x / tpc;
+    const int tile = blockIdx.x % tpc;
+    const int c = list ? list[ci] : ci;
     const int64_t d0 = g.dof_ptr[c];
     const int n = int(g.dof_ptr[c + 1] - d0);
-    const int r0 = tile * 256;
+    const int r0 = tile * kWave;
     if (r0 >= n) return;
-    const int ng = min(4, (n - r0 + 63) / 64);
-    const double *__restrict__ A = g.minv + g.minv_ptr[c];
+    if (bytes != nullptr && threadIdx.x == 0) {
+        const unsigned long long rows = unsigned(min(kWave, n - r0));
+        atomicAdd(bytes, 8ull * (rows * unsigned(n) + rows * NC + (tile == 0 ? unsigned(n) * NC : 0u)));
+    }
+    const int row = r0 + lane;
+    const bool ok = row < n;
+    const int rowc = ok ? row : n - 1;  // clamped: out-of-range lanes read a valid address
+    const double *__restrict__ A = g.minv + g.minv_ptr[c] + rowc;
     const double *__restrict__ B = X + d0 * NC;
-    double acc[4][NC];
+    const int span = (n + 3) / 4;
+    const int j0 = min(n, wv * span), j1 = min(n, j0 + span);
+    double acc[NC];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int col = 0; col < NC; ++col) acc[col] = 0.0;
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+        const double m0 = A[int64_t(j) * n], m1 = A[int64_t(j + 1) * n];
+        const double m2 = A[int64_t(j + 2) * n], m3 = A[int64_t(j + 3) * n];
+        const double *b = B + int64_t(j) * NC;
 #pragma unroll
-        for (int col = 0; col < NC; ++col) acc[i][col] = 0.0;
-    int row[4];
-    bool ok[4];
+        for (int col = 0; col < NC; ++col) acc[col] = fma(m0, b[col], acc[col]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        row[i] = r0 + 64 * i + lane;
-        ok[i] = row[i] < n;
+        for (int col = 0; col < NC; ++col) acc[col] = fma(m1, b[NC + col], acc[col]);
+#pragma unroll
+        for (int col = 0; col < NC; ++col) acc[col] = fma(m2, b[2 * NC + col], acc[col]);
+#pragma unroll
+        for (int col = 0; col < NC; ++col) acc[col] = fma(m3, b[3 * NC + col], acc[col]);
     }
-    for (int j = 0; j < n; ++j) {
-        double b[NC];
+    for (; j < j1; ++j) {
+        const double m0 = A[int64_t(j) * n];
+        const double *b = B + int64_t(j) * NC;
 #pragma unroll
-        for (int col = 0; col < NC; ++col) b[col] = B[int64_t(j) * NC + col];
-        const double *Aj = A + int64_t(j) * n;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            if (i < ng) {
-                const double mij = ok[i] ? Aj[row[i]] : 0.0;
-#pragma unroll
-                for (int col = 0; col < NC; ++col) acc[i][col] = fma(mij, b[col], acc[i][col]);
-            }
-        }
+        for (int col = 0; col < NC; ++col) acc[col] = fma(m0, b[col], acc[col]);
     }
+    if (wv > 0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        if (i < ng && ok[i]) {
-            if (MODE == 0) {
+        for (int col = 0; col < NC; ++col) part[wv - 1][col][lane] = acc[col];
+    }
+    __syncthreads();
+    if (wv == 0 && ok) {
 #pragma unroll
-                for (int col = 0; col < NC; ++col) Y[(d0 + row[i]) * NC + col] = acc[i][col];
-            } else {
-#pragma unroll
-                for (int col = 0; col < NC; ++col) Y[col * g.ndof + d0 + row[i]] += acc[i][col];
-            }
+        for (int col = 0; col < NC; ++col) {
+            const double v = ((acc[col] + part[0][col][lane]) + part[1][col][lane]) + part[2][col][lane];
+            if (MODE == 0)
+                Y[(d0 + row) * NC + col] = v;
+            else
+                Y[col * g.ndof + d0 + row] += v;
         }
     }
 }
 
-// One block per active cell: G(x) = u - (K_tau^{-1} (x) I) S  (eq:ader4 after
-// K_1^{-1} = K_tau^{-1} (x) M_i^{-1}), the residual test, and the Anderson
-// update x <- G(x) - dG gamma, gamma = argmin |f - dF gamma|.  The history of
-// difference pairs is append-only (restarted when full), so the Gram matrix of
-// dF only gains a row per iteration; its Jacobi-scaled Cholesky factor is
-// extended by one row, a column that adds no new direction is not appended.
-// Depth 0 is the plain fixed-point map.
+// Anderson acceleration of the predictor map (eq:ader4 after
+// K_1^{-1} = K_tau^{-1} (x) M_i^{-1}): G(x) = u - (K_tau^{-1} (x) I) S with
+// S = M_i^{-1} R(x), residual f = G(x) - x, and x <- G(x) - dG gamma with
+// gamma = argmin |f - dF gamma|.  Three kernels per iteration:
+//   k_and_dots   (blocks of 64 DOFs of each listed cell): G, f, the new
+//                difference pair into the ring, partial dot products of the
+//                history with the new column and with f, partial max norms;
+//   k_and_solve  (one wave per listed cell): reduces the partials in tile
+//                order, tests convergence, extends (or rebuilds after dropping
+//                the oldest pairs) the Jacobi-scaled Cholesky factor of the
+//                Gram matrix of dF, solves for gamma, builds the next list;
+//   k_and_update (blocks of 64 DOFs): x <- G(x) - sum_j gamma_j dG_j.
+// Difference pairs live in a ring of `depth` slots, logical order oldest
+// first; a column adding no new direction is not appended; when the ring is
+// full the 8 oldest pairs are dropped.  Depth 0 is the plain fixed-point map.
+constexpr int kDrop = 8;
+constexpr int kPartStride = 2 * (kMaxDepth + 1) + 2;
+
+// history bookkeeping shared by the three kernels: (count kept, head slot)
+__device__ inline void ring_state(const DevWork &w, int c, int &k, int &head, bool &dropped) {
+    k = w.hist[2 * c];
+    head = k == 0 ? 0 : w.hist[2 * c + 1];
+    dropped = false;
+    if (k >= w.depth && w.depth > 0) {
+        const int drop = min(kDrop, k);
+        head = (head + drop) % w.depth;
+        k -= drop;
+        dropped = true;
+    }
+}
+
 template <int N>
-__global__ void __launch_bounds__(256) k_anderson(DevGrid g, DevWork w, const double *__restrict__ u, int it,
-                                                   int max_iter, double tol) {
+__global__ void __launch_bounds__(256) k_and_dots(DevGrid g, DevWork w, const double *__restrict__ u, int it,
+                                                  const int32_t *__restrict__ list, int tpc) {
     constexpr int nc = Dim<N>::nc, nt = Dim<N>::nt;
-    constexpr int kChunk = 4;  // elements per thread per chunk of the dot products
-    __shared__ double red[2][4];
-    __shared__ double accH[kMaxDepth + 1][4], accB[kMaxDepth + 1][4];
-    __shared__ double gam_s[kMaxDepth];
-    __shared__ int kuse_s;
-    const int c = blockIdx.x;
-    if (!w.active[c]) return;
-    const int tid = threadIdx.x, nth = blockDim.x, lane = tid % kWave, wv = tid / kWave;
-    const int nw = nth / kWave;
+    constexpr int kPer = (64 * nc + 255) / 256;  // elements per thread
+    __shared__ double accs[2 * (kMaxDepth + 1) + 2][4];
+    const int c = list[blockIdx.x / tpc];
+    const int tile = blockIdx.x % tpc;
     const int64_t d0 = g.dof_ptr[c];
     const int n = int(g.dof_ptr[c + 1] - d0);
+    if (tile * 64 >= n) return;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
+    const int depth = w.depth;
+    const bool hist_on = depth > 0 && it > 0;
+    int k = 0, head = 0;
+    bool dropped = false;
+    if (hist_on) ring_state(w, c, k, head, dropped);
+    const int snew = hist_on ? (head + k) % depth : 0;
     const int64_t len = int64_t(n) * nc;
     const int64_t base = d0 * nc;
-    const int64_t nd = g.ndof;
-    double Ki[nt * nt];
-    for (int i = 0; i < nt * nt; ++i) Ki[i] = g.ref->Ktau_inv[i];
+    double *dF = w.dF + base * depth;
+    double *dG = w.dG + base * depth;
+    const int64_t e0 = int64_t(tile) * 64 * nc;
+    const int64_t e1 = min(len, e0 + int64_t(64) * nc);
+    double fe[kPer], dfe[kPer];
+    int64_t ie[kPer];
     double fmx = 0.0, gmx = 0.0;
-    for (int l = tid; l < n; l += nth) {
-        double s[nc];
-        for (int i = 0; i < nc; ++i) s[i] = w.S[base + int64_t(l) * nc + i];
-        for (int b = 0; b < nt; ++b)
-            for (int v = 0; v < 5; ++v) {
-                double acc = 0.0;
-                for (int a2 = 0; a2 < nt; ++a2) acc += Ki[b * nt + a2] * s[a2 * 5 + v];
-                const double gv = u[v * nd + d0 + l] - acc;
-                const int64_t idx = base + int64_t(l) * nc + b * 5 + v;
-                const double fv = gv - w.x[idx];
-                w.gcur[idx] = gv;
-                w.fcur[idx] = fv;
-                fmx = fmax(fmx, fabs(fv));
-                gmx = fmax(gmx, fabs(gv));
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        ie[q] = e0 + int64_t(q) * 256 + tid;
+        fe[q] = dfe[q] = 0.0;
+        if (ie[q] < e1) {
+            const int64_t e = ie[q];
+            const int l = int(e / nc);
+            const int col = int(e % nc);
+            const int b = col / 5, v = col % 5;
+            const double *sr = w.S + base + int64_t(l) * nc + v;
+            double acc = 0.0;
+#pragma unroll
+            for (int a = 0; a < nt; ++a) acc += g.ref->Ktau_inv[b * nt + a] * sr[a * 5];
+            const double gv = u[v * g.ndof + d0 + l] - acc;
+            const double fv = gv - w.x[base + e];
+            fmx = fmax(fmx, fabs(fv));
+            gmx = fmax(gmx, fabs(gv));
+            if (hist_on) {
+                const double dfn = fv - w.fprev[base + e];
+                dF[int64_t(snew) * len + e] = dfn;
+                dG[int64_t(snew) * len + e] = gv - w.gprev[base + e];
+                dfe[q] = dfn;
             }
+            fe[q] = fv;
+            w.fprev[base + e] = fv;
+            w.gprev[base + e] = gv;
+        }
     }
+    double *part = w.part + (int64_t(c) * tpc + tile) * kPartStride;
     fmx = wave_max(fmx);
     gmx = wave_max(gmx);
     if (lane == 0) {
-        red[0][wv] = fmx;
-        red[1][wv] = gmx;
+        accs[0][wv] = fmx;
+        accs[1][wv] = gmx;
     }
-    __syncthreads();
-    double res = 0.0, gm = 0.0;
-    for (int i = 0; i < nw; ++i) {
-        res = fmax(res, red[0][i]);
-        gm = fmax(gm, red[1][i]);
-    }
-    const int it1 = it + 1;
-    const bool conv = res <= tol * fmax(1.0, gm);
-    const bool last = it1 >= max_iter;
-    const int depth = w.depth;
-    if (conv || last || depth == 0 || it == 0) {
-        for (int64_t i = tid; i < len; i += nth) {
-            const double gv = w.gcur[base + i];
-            w.x[base + i] = gv;
-            if (!(conv || last)) {
-                w.fprev[base + i] = w.fcur[base + i];
-                w.gprev[base + i] = gv;
-            }
-        }
-        if (tid == 0) {
-            w.iters[c] = it1;
-            w.hist[2 * c] = 0;
-            if (conv || last) {
-                w.active[c] = 0;
-                atomicSub(&w.status[2], 1);
-                if (!conv) {
-                    atomicOr(&w.status[0], kStatusNoConv);
-                    atomicMin(&w.status[1], c);
-                }
-            }
-        }
-        return;
-    }
-    int k = w.hist[2 * c];
-    if (k >= depth) k = 0;  // restart with the newest pair only
-    const int64_t hoff = base * depth;
-    double *dF = w.dF + hoff;
-    double *dG = w.dG + hoff;
-    double *Lc = w.gram + int64_t(c) * kMaxDepth * kMaxDepth;  // Cholesky rows, row-major
-    double *dsc = w.gram + int64_t(g.n_cells) * kMaxDepth * kMaxDepth + int64_t(c) * kMaxDepth;
-    for (int j = tid; j <= k; j += nth) {
-        accH[j][0] = accH[j][1] = accH[j][2] = accH[j][3] = 0.0;
-        accB[j][0] = accB[j][1] = accB[j][2] = accB[j][3] = 0.0;
-    }
-    __syncthreads();
-    // new difference pair (slot k) and the dots <dF_j, dF_new>, <dF_j, f>
-    for (int64_t c0 = 0; c0 < len; c0 += int64_t(nth) * kChunk) {
-        double fe[kChunk], dfe[kChunk];
-        int64_t ie[kChunk];
-#pragma unroll
-        for (int e = 0; e < kChunk; ++e) {
-            ie[e] = c0 + int64_t(e) * nth + tid;
-            fe[e] = dfe[e] = 0.0;
-            if (ie[e] < len) {
-                const double f = w.fcur[base + ie[e]];
-                const double dfn = f - w.fprev[base + ie[e]];
-                fe[e] = f;
-                dfe[e] = dfn;
-                dF[int64_t(k) * len + ie[e]] = dfn;
-                dG[int64_t(k) * len + ie[e]] = w.gcur[base + ie[e]] - w.gprev[base + ie[e]];
-            }
-        }
+    if (hist_on) {
         for (int j = 0; j <= k; ++j) {
+            const int sj = (head + j) % depth;
             double ph = 0.0, pb = 0.0;
 #pragma unroll
-            for (int e = 0; e < kChunk; ++e) {
-                const double d = (j == k) ? dfe[e] : (ie[e] < len ? dF[int64_t(j) * len + ie[e]] : 0.0);
-                ph = fma(d, dfe[e], ph);
-                pb = fma(d, fe[e], pb);
+            for (int q = 0; q < kPer; ++q) {
+                if (ie[q] < e1) {
+                    const double d = (j == k) ? dfe[q] : dF[int64_t(sj) * len + ie[q]];
+                    ph = fma(d, dfe[q], ph);
+                    pb = fma(d, fe[q], pb);
+                }
             }
             ph = wave_sum(ph);
             pb = wave_sum(pb);
             if (lane == 0) {
-                accH[j][wv] += ph;
-                accB[j][wv] += pb;
+                accs[2 + j][wv] = ph;
+                accs[2 + kMaxDepth + 1 + j][wv] = pb;
             }
         }
     }
     __syncthreads();
-    if (wv == 0) {
-        // one wave: extend the scaled Cholesky factor by row k, solve for gamma
-        const double hkk = accH[k][0] + accH[k][1] + accH[k][2] + accH[k][3];
-        const double dk = hkk > 0.0 ? 1.0 / sqrt(hkk) : 0.0;
-        // lane j holds entries of index j (k <= kMaxDepth - 1 < 64)
-        const double hj = (lane < k) ? (accH[lane][0] + accH[lane][1] + accH[lane][2] + accH[lane][3]) : 0.0;
-        const double dj = (lane < k) ? dsc[lane] : 0.0;
-        const double rhs = hj * dj * dk;  // scaled Gram row
-        double y = 0.0;                   // solve L[0:k,0:k] y = rhs by forward substitution
-        for (int i = 0; i < k; ++i) {
-            const double lij = (lane < i) ? Lc[i * kMaxDepth + lane] : 0.0;
-            const double s = wave_sum(lij * y);
-            const double yi = (__shfl(rhs, i, kWave) - s) / Lc[i * kMaxDepth + i];
-            if (lane == i) y = yi;
+    const int nv = hist_on ? 2 * (kMaxDepth + 1) + 2 : 2;
+    for (int t = tid; t < nv; t += blockDim.x) {
+        const bool used = t < 2 || (t >= 2 && t < 2 + k + 1) || (t >= 2 + kMaxDepth + 1 && t < 2 + kMaxDepth + 1 + k + 1);
+        if (!used) continue;
+        double r = accs[t][0];
+        if (t < 2) {
+            r = fmax(fmax(r, accs[t][1]), fmax(accs[t][2], accs[t][3]));
+        } else {
+            r = ((r + accs[t][1]) + accs[t][2]) + accs[t][3];
         }
-        const double ysq = wave_sum(lane < k ? y * y : 0.0);
-        const double diag = 1.0 + 1e-12 - ysq;
-        const bool add = (hkk > 0.0) && (diag > 1e-10);
-        const int kuse = add ? k + 1 : k;
-        if (add) {
-            if (lane < k) Lc[k * kMaxDepth + lane] = y;
-            if (lane == 0) {
-                Lc[k * kMaxDepth + k] = sqrt(diag);
-                dsc[k] = dk;
-            }
+        part[t] = r;
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(64) k_and_solve(DevGrid g, DevWork w, int it, int max_iter, double tol,
+                                                  const int32_t *__restrict__ list, int tpc, int32_t *next,
+                                                  int32_t *next_count) {
+    const int c = list[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int n = int(g.dof_ptr[c + 1] - g.dof_ptr[c]);
+    const int ntile = (n + 63) / 64;
+    const double *part = w.part + int64_t(c) * tpc * kPartStride;
+    const int depth = w.depth;
+    const bool hist_on = depth > 0 && it > 0;
+    // reduce the per-tile partials in tile order
+    double res = 0.0, gm = 0.0;
+    for (int t = 0; t < ntile; ++t) {
+        res = fmax(res, part[t * kPartStride + 0]);
+        gm = fmax(gm, part[t * kPartStride + 1]);
+    }
+    const int it1 = it + 1;
+    const bool conv = res <= tol * fmax(1.0, gm);
+    const bool last = it1 >= max_iter;
+    double *gam = w.gamma + int64_t(c) * kMaxDepth;
+    if (lane == 0) {
+        w.iters[c] = it1;
+        if (!(conv || last)) next[atomicAdd(next_count, 1)] = c;
+        if (last && !conv) {
+            atomicOr(&w.status[0], kStatusNoConv);
+            atomicMin(&w.status[1], c);
         }
-        __threadfence_block();
-        // gamma: (D H D + reg) z = D b, gamma = D z
-        const double bj = (lane < kuse) ? (accB[lane][0] + accB[lane][1] + accB[lane][2] + accB[lane][3]) *
-                                              ((lane == k) ? dk : dsc[lane < k ? lane : 0])
-                                        : 0.0;
-        double z = 0.0;
-        for (int i = 0; i < kuse; ++i) {
-            const double lij = (lane < i) ? ((i == k && add) ? y : Lc[i * kMaxDepth + lane]) : 0.0;
-            const double s = wave_sum(lij * z);
-            const double lii = (i == k && add) ? sqrt(diag) : Lc[i * kMaxDepth + i];
-            const double zi = (__shfl(bj, i, kWave) - s) / lii;
-            if (lane == i) z = zi;
-        }
-        double x = 0.0;
-        for (int i = kuse - 1; i >= 0; --i) {
-            // L^T x = z: x_i = (z_i - sum_{j > i} L[j][i] x_j) / L[i][i]
-            const double yi_new = __shfl(y, i, kWave);  // L[k][i] of the new row
-            const double lji = (lane > i && lane < kuse) ? ((lane == k && add) ? yi_new : Lc[lane * kMaxDepth + i]) : 0.0;
-            const double s = wave_sum(lji * x);
-            const double lii = (i == k && add) ? sqrt(diag) : Lc[i * kMaxDepth + i];
-            const double xi = (__shfl(z, i, kWave) - s) / lii;
-            if (lane == i) x = xi;
-        }
-        if (lane < kuse) gam_s[lane] = x * ((lane == k) ? dk : dsc[lane < k ? lane : 0]);
+    }
+    if (conv || last || !hist_on) {
         if (lane == 0) {
-            kuse_s = kuse;
-            w.hist[2 * c] = kuse;
-            w.iters[c] = it1;
+            w.hist[2 * c] = 0;
+            w.hist[2 * c + 1] = 0;
+            w.kuse[c] = 0;
+        }
+        return;
+    }
+    int k, head;
+    bool dropped;
+    ring_state(w, c, k, head, dropped);
+    const int64_t cells_sq = int64_t(g.n_cells) * kMaxDepth * kMaxDepth;
+    double *Lc = w.gram + int64_t(c) * kMaxDepth * kMaxDepth;             // scaled Cholesky, logical rows
+    double *Hc = w.gram + cells_sq + int64_t(c) * kMaxDepth * kMaxDepth;  // Gram of dF, by slot
+    double *dsc = w.gram + 2 * cells_sq + int64_t(c) * kMaxDepth;         // column scales, by slot
+    if (dropped) {
+        for (int i = 0; i < k; ++i) {
+            const int si = (head + i) % depth;
+            const int sl = (head + lane) % depth;
+            const double rhs = (lane < i) ? Hc[si * kMaxDepth + sl] * dsc[si] * dsc[sl] : 0.0;
+            double y = 0.0;
+            for (int r = 0; r < i; ++r) {
+                const double lrj = (lane < r) ? Lc[r * kMaxDepth + lane] : 0.0;
+                const double sm = wave_sum(lrj * y);
+                const double yr = (__shfl(rhs, r, kWave) - sm) / Lc[r * kMaxDepth + r];
+                if (lane == r) y = yr;
+            }
+            const double ysq = wave_sum(lane < i ? y * y : 0.0);
+            if (lane < i) Lc[i * kMaxDepth + lane] = y;
+            if (lane == 0) Lc[i * kMaxDepth + i] = sqrt(fmax(1.0 + 1e-12 - ysq, 1e-10));
+            __threadfence_block();
         }
     }
-    __syncthreads();
-    const int kuse = kuse_s;
-    for (int64_t i = tid; i < len; i += nth) {
-        double xv = w.gcur[base + i];
-        for (int j = 0; j < kuse; ++j) xv -= gam_s[j] * dG[int64_t(j) * len + i];
-        w.x[base + i] = xv;
-        w.fprev[base + i] = w.fcur[base + i];
-        w.gprev[base + i] = w.gcur[base + i];
+    // reduced dots: h_j = <dF_j, dF_new>, b_j = <dF_j, f>, j = 0..k (k = new column)
+    double hj = 0.0, bj_raw = 0.0;
+    if (lane <= k) {
+        for (int t = 0; t < ntile; ++t) {
+            hj += part[t * kPartStride + 2 + lane];
+            bj_raw += part[t * kPartStride + 2 + kMaxDepth + 1 + lane];
+        }
+    }
+    const int snew = (head + k) % depth;
+    const double hkk = __shfl(hj, k, kWave);
+    const double dk = hkk > 0.0 ? 1.0 / sqrt(hkk) : 0.0;
+    const int sl = (head + (lane < k ? lane : 0)) % depth;
+    const double dj = (lane < k) ? dsc[sl] : 0.0;
+    const double rhs = (lane < k) ? hj * dj * dk : 0.0;
+    double y = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double lij = (lane < i) ? Lc[i * kMaxDepth + lane] : 0.0;
+        const double sm = wave_sum(lij * y);
+        const double yi = (__shfl(rhs, i, kWave) - sm) / Lc[i * kMaxDepth + i];
+        if (lane == i) y = yi;
+    }
+    const double ysq = wave_sum(lane < k ? y * y : 0.0);
+    const double diag = 1.0 + 1e-12 - ysq;
+    const bool add = (hkk > 0.0) && (diag > 1e-10);
+    const int kuse = add ? k + 1 : k;
+    if (add) {
+        if (lane < k) {
+            Lc[k * kMaxDepth + lane] = y;
+            Hc[snew * kMaxDepth + sl] = hj;
+            Hc[sl * kMaxDepth + snew] = hj;
+        }
+        if (lane == 0) {
+            Lc[k * kMaxDepth + k] = sqrt(diag);
+            Hc[snew * kMaxDepth + snew] = hkk;
+            dsc[snew] = dk;
+        }
+    }
+    __threadfence_block();
+    const double scl = (lane < k) ? dj : ((lane == k) ? dk : 0.0);
+    const double bj = (lane < kuse) ? bj_raw * scl : 0.0;
+    double z = 0.0;
+    for (int i = 0; i < kuse; ++i) {
+        const double lij = (lane < i) ? ((i == k) ? y : Lc[i * kMaxDepth + lane]) : 0.0;
+        const double sm = wave_sum(lij * z);
+        const double lii = (i == k) ? sqrt(diag) : Lc[i * kMaxDepth + i];
+        const double zi = (__shfl(bj, i, kWave) - sm) / lii;
+        if (lane == i) z = zi;
+    }
+    double xs = 0.0;
+    for (int i = kuse - 1; i >= 0; --i) {
+        const double yi_new = __shfl(y, i, kWave);  // L[k][i] of the new row
+        const double lji = (lane > i && lane < kuse) ? ((lane == k) ? yi_new : Lc[lane * kMaxDepth + i]) : 0.0;
+        const double sm = wave_sum(lji * xs);
+        const double lii = (i == k) ? sqrt(diag) : Lc[i * kMaxDepth + i];
+        const double xi = (__shfl(z, i, kWave) - sm) / lii;
+        if (lane == i) xs = xi;
+    }
+    if (lane < kuse) gam[lane] = xs * scl;
+    if (lane == 0) {
+        w.kuse[c] = kuse;
+        w.hist[2 * c] = kuse;
+        w.hist[2 * c + 1] = head;
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_and_update(DevGrid g, DevWork w, const int32_t *__restrict__ list,
+                                                    int tpc) {
+    constexpr int nc = Dim<N>::nc;
+    const int c = list[blockIdx.x / tpc];
+    const int tile = blockIdx.x % tpc;
+    const int64_t d0 = g.dof_ptr[c];
+    const int n = int(g.dof_ptr[c + 1] - d0);
+    if (tile * 64 >= n) return;
+    const int64_t len = int64_t(n) * nc;
+    const int64_t base = d0 * nc;
+    const int kuse = w.kuse[c];
+    const int depth = w.depth;
+    const int head = w.hist[2 * c + 1];
+    const double *gam = w.gamma + int64_t(c) * kMaxDepth;
+    const double *dG = w.dG + base * (depth > 0 ? depth : 1);
+    const int64_t e0 = int64_t(tile) * 64 * nc;
+    const int64_t e1 = min(len, e0 + int64_t(64) * nc);
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        double xv = w.gprev[base + e];
+        for (int j = 0; j < kuse; ++j) xv -= gam[j] * dG[int64_t((head + j) % depth) * len + e];
+        w.x[base + e] = xv;
     }
 }
 
@@ -819,16 +927,27 @@ hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, const double *u,
 }
 
 hipError_t launch_pred_iteration(const DevGrid &g, const DevWork &w, const double *u, double dt, int it,
-                                 int max_iter, double tol, hipStream_t s) {
+                                 int max_iter, double tol, const int32_t *list, int n_list, int32_t *next,
+                                 int32_t *next_count, hipStream_t s, const ProfileHooks *prof) {
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        hipLaunchKernelGGL((k_subtet<NN, false>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w, dt);
-        hipLaunchKernelGGL(k_gather<NN>, dim3(blocks_for(g.ndof * D::nc, 256)), dim3(256), 0, s, g, w);
-        const int tpc = (g.max_cell_dofs + 255) / 256;
-        hipLaunchKernelGGL((k_minv<D::nc, 0>), dim3(blocks_for(int64_t(g.n_cells) * tpc, 4)), dim3(256), 0, s, g,
-                           w.active, w.R, w.S, tpc);
-        hipLaunchKernelGGL(k_anderson<NN>, dim3(g.n_cells), dim3(256), 0, s, g, w, u, it, max_iter, tol);
+        const int chunks = (g.max_cell_subtets + D::spb - 1) / D::spb;
+        hipLaunchKernelGGL((k_subtet<NN, false>), dim3(unsigned(n_list) * chunks), dim3(D::threads), 0, s, g, w, dt,
+                           list, chunks);
+        const int per = int((int64_t(g.max_cell_dofs) * D::nc + 255) / 256);
+        hipLaunchKernelGGL(k_gather<NN>, dim3(unsigned(n_list) * per), dim3(256), 0, s, g, w, list, per);
+        const int tpc = (g.max_cell_dofs + 63) / 64;
+        if (prof) (void)hipEventRecord(prof->start, s);
+        hipLaunchKernelGGL((k_minv<D::nc, 0>), dim3(unsigned(n_list) * tpc), dim3(256), 0, s, g, list, w.R, w.S, tpc,
+                           prof ? prof->bytes : nullptr);
+        if (prof) (void)hipEventRecord(prof->stop, s);
+        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, next_count);
+        const int tpd = (g.max_cell_dofs + 63) / 64;
+        hipLaunchKernelGGL(k_and_dots<NN>, dim3(unsigned(n_list) * tpd), dim3(256), 0, s, g, w, u, it, list, tpd);
+        hipLaunchKernelGGL(k_and_solve<NN>, dim3(unsigned(n_list)), dim3(64), 0, s, g, w, it, max_iter, tol, list,
+                           tpd, next, next_count);
+        hipLaunchKernelGGL(k_and_update<NN>, dim3(unsigned(n_list) * tpd), dim3(256), 0, s, g, w, list, tpd);
         return hipGetLastError();
     });
 }
@@ -837,7 +956,8 @@ hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, double dt, hipSt
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        hipLaunchKernelGGL((k_subtet<NN, true>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w, dt);
+        hipLaunchKernelGGL((k_subtet<NN, true>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w, dt,
+                           nullptr, 1);
         return hipGetLastError();
     });
 }
@@ -848,9 +968,9 @@ hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, double 
         using D = Dim<NN>;
         hipLaunchKernelGGL(k_face<NN>, dim3(blocks_for(g.nsub, 256 / D::nf)), dim3(256), 0, s, g, w, dt);
         hipLaunchKernelGGL(k_rhs<NN>, dim3(blocks_for(g.ndof * 5, 256)), dim3(256), 0, s, g, w);
-        const int tpc = (g.max_cell_dofs + 255) / 256;
-        hipLaunchKernelGGL((k_minv<5, 1>), dim3(blocks_for(int64_t(g.n_cells) * tpc, 4)), dim3(256), 0, s, g,
-                           w.active, w.rhs, u, tpc);
+        const int tpc = (g.max_cell_dofs + 63) / 64;
+        hipLaunchKernelGGL((k_minv<5, 1>), dim3(unsigned(g.n_cells) * tpc), dim3(256), 0, s, g, nullptr, w.rhs, u,
+                           tpc, nullptr);
         hipLaunchKernelGGL(k_positivity, dim3(blocks_for(g.ndof, 256)), dim3(256), 0, s, g, w, u);
         return hipGetLastError();
     });
