@@ -58,18 +58,30 @@ def measured_traffic(workload: str, achieved_bytes_per_launch: float):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(mesh, N, u0_np, dt, budget_s: float = 20.0):
+def cpu_baseline(mesh, N, u0_np, dt, budget_s: float = 20.0, cluster_size: int = 48):
     """Time the CPU oracle on a bounded sample of the same workload and
     extrapolate its full-step DOF-updates/s: predictor + time integrals on a
-    cluster of cells and their neighbours, corrector on the cluster."""
+    cluster of cells (breadth-first from cell 0) and their neighbours, the
+    corrector on the cluster."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle.scheme import Oracle, Params
 
     n_cells = mesh["n_cells"]
-    # a cluster: cell 0 and its face neighbours
-    cluster = [0]
+    nbrs = [[] for _ in range(n_cells)]
+    for a, b in mesh["face_cell"]:
+        nbrs[int(a)].append(int(b))
+        nbrs[int(b)].append(int(a))
+    cluster, seen = [], {0}
+    frontier = [0]
+    while frontier and len(cluster) < cluster_size:
+        c = frontier.pop(0)
+        cluster.append(c)
+        for x in nbrs[c]:
+            if x not in seen:
+                seen.add(x)
+                frontier.append(x)
     o = Oracle(mesh, N, Params(), cells=cluster)
     ring = o.ring()
     with threadpool_limits(limits=1):
@@ -115,6 +127,8 @@ def main() -> int:
     ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -144,6 +158,14 @@ def main() -> int:
     prim = torch.tensor(density_wave(np.mod(x.cpu().numpy().T, 1.0)).T.copy(), device="cuda")
     u = cd.prim_to_cons(prim)
     u0 = u.clone()
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * 2**20 // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n * 8} bytes read, {n * 8} bytes written")
+        del src, dst
 
     def one_step():
         dt = cd.cfl_dt(u, args.cfl)

@@ -87,7 +87,7 @@ size_t estimate_bytes(const afe::HostGrid &h, int depth) {
     size_t b = 0;
     for (int c = 0; c < h.n_cells; ++c) {
         size_t n = size_t(h.dof_ptr[c + 1] - h.dof_ptr[c]);
-        b += n * n * sizeof(double);
+        b += n * ((n + 15) & ~size_t(15)) * sizeof(double);
     }
     b += size_t(h.ndof) * nc * sizeof(double) * (5 + 2 * size_t(std::max(depth, 1)));
     b += size_t(h.n_cells) * ((h.max_cell_dofs + 63) / 64) * 130 * sizeof(double);
@@ -153,7 +153,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     std::vector<int64_t> minv_ptr(h.n_cells + 1, 0);
     for (int c = 0; c < h.n_cells; ++c) {
         int64_t n = h.dof_ptr[c + 1] - h.dof_ptr[c];
-        minv_ptr[c + 1] = minv_ptr[c] + n * n;
+        minv_ptr[c + 1] = minv_ptr[c] + n * ((n + 15) & ~int64_t(15));  // rows padded to 128 bytes
     }
     hipError_t e;
     if ((e = cd->upload(g.dof_ptr, h.dof_ptr, s)) != hipSuccess ||

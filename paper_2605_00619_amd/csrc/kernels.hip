@@ -44,6 +44,21 @@ __device__ inline double wave_min(double v) {
     return v;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// The per-cell kernels use several blocks per cell that share the cell's
+// operands; this bijection gives every XCD a contiguous range of logical block
+// ids, so the blocks of one cell run on one XCD and share its L2.
+__device__ inline int xcd_block() {
+    constexpr int kXcd = 8;
+    const int bid = blockIdx.x, nb = gridDim.x;
+    const int q = nb / kXcd, r = nb % kXcd;
+    const int x = bid % kXcd, local = bid / kXcd;
+    return x * q + min(x, r) + local;
+}
+
+// Leading dimension of the stored M_i^{-1}: rows padded to 128 bytes.
+__device__ __host__ inline int64_t minv_ld(int64_t n) { return (n + 15) & ~int64_t(15); }
+
 // Physical flux F[x][v] of the compressible Navier-Stokes equations (Sec. 2)
 // at one point.  gq[x][v] = d q_v / d x_x is used only when mu != 0; heat
 // conduction is zero.
@@ -83,15 +98,16 @@ __global__ void __launch_bounds__(256) k_mass_assemble(DevGrid g) {
     constexpr int np = Dim<N>::np;
     const int c = blockIdx.x;
     const int64_t n = g.dof_ptr[c + 1] - g.dof_ptr[c];
+    const int64_t ld = minv_ld(n);
     double *M = g.minv + g.minv_ptr[c];
-    for (int64_t e = threadIdx.x; e < n * n; e += blockDim.x) M[e] = 0.0;
+    for (int64_t e = threadIdx.x; e < n * ld; e += blockDim.x) M[e] = 0.0;
     __syncthreads();
     for (int64_t k = g.sub_ptr[c]; k < g.sub_ptr[c + 1]; ++k) {
         const double dj = g.geo[k * 10 + 9];
         for (int t = threadIdx.x; t < np * np; t += blockDim.x) {
             const int m = t / np, p = t % np;
             const int64_t i = g.conn[k * np + m], j = g.conn[k * np + p];
-            M[i * n + j] += dj * g.ref->M[m * np + p];
+            M[i * ld + j] += dj * g.ref->M[m * np + p];
         }
         __syncthreads();
     }
@@ -105,27 +121,28 @@ __global__ void __launch_bounds__(1024) k_mass_invert(DevGrid g) {
     const int c = blockIdx.x;
     const int n = int(g.dof_ptr[c + 1] - g.dof_ptr[c]);
     double *A = g.minv + g.minv_ptr[c];
+    const int64_t ld = minv_ld(n);
     double *dsc = sh;
     double *rowk = sh + n;
     double *colk = sh + 2 * n;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int tx = tid % 64, ty = tid / 64, ny = nth / 64;
-    for (int i = tid; i < n; i += nth) dsc[i] = 1.0 / sqrt(A[int64_t(i) * n + i]);
+    for (int i = tid; i < n; i += nth) dsc[i] = 1.0 / sqrt(A[int64_t(i) * ld + i]);
     __syncthreads();
     for (int i = ty; i < n; i += ny)
-        for (int j = tx; j < n; j += 64) A[int64_t(i) * n + j] *= dsc[i] * dsc[j];
+        for (int j = tx; j < n; j += 64) A[int64_t(i) * ld + j] *= dsc[i] * dsc[j];
     __syncthreads();
     for (int k = 0; k < n; ++k) {
-        const double piv = A[int64_t(k) * n + k];
+        const double piv = A[int64_t(k) * ld + k];
         const double ip = 1.0 / piv;
         for (int j = tid; j < n; j += nth) {
-            rowk[j] = (j == k ? 1.0 : A[int64_t(k) * n + j]) * ip;
-            colk[j] = (j == k ? 0.0 : A[int64_t(j) * n + k]);
+            rowk[j] = (j == k ? 1.0 : A[int64_t(k) * ld + j]) * ip;
+            colk[j] = (j == k ? 0.0 : A[int64_t(j) * ld + k]);
         }
         __syncthreads();
         for (int i = ty; i < n; i += ny) {
             const double ci = colk[i];
-            double *Ai = A + int64_t(i) * n;
+            double *Ai = A + int64_t(i) * ld;
             if (i == k) {
                 for (int j = tx; j < n; j += 64) Ai[j] = rowk[j];
             } else {
@@ -137,9 +154,9 @@ __global__ void __launch_bounds__(1024) k_mass_invert(DevGrid g) {
     for (int i = ty; i < n; i += ny)
         for (int j = tx; j < n; j += 64) {
             if (j < i) continue;
-            const double v = 0.5 * (A[int64_t(i) * n + j] + A[int64_t(j) * n + i]) * dsc[i] * dsc[j];
-            A[int64_t(i) * n + j] = v;
-            A[int64_t(j) * n + i] = v;
+            const double v = 0.5 * (A[int64_t(i) * ld + j] + A[int64_t(j) * ld + i]) * dsc[i] * dsc[j];
+            A[int64_t(i) * ld + j] = v;
+            A[int64_t(j) * ld + i] = v;
         }
 }
 
@@ -290,8 +307,9 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
         if (valid) c = g.sub_cell[k];
     } else {
         // block -> (active cell, chunk of spb of its sub-tets)
-        c = list[blockIdx.x / chunks];
-        k = g.sub_ptr[c] + int64_t(blockIdx.x % chunks) * spb + s;
+        const int lb = xcd_block();
+        c = list[lb / chunks];
+        k = g.sub_ptr[c] + int64_t(lb % chunks) * spb + s;
         valid = (s < spb) && (k < g.sub_ptr[c + 1]);
     }
     double G[9], dj = 0.0, mu_c = 0.0;
@@ -386,9 +404,10 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
 template <int N>
 __global__ void __launch_bounds__(256) k_gather(DevGrid g, DevWork w, const int32_t *__restrict__ list, int per) {
     constexpr int nc = Dim<N>::nc;
-    const int c = list[blockIdx.x / per];
+    const int lb = xcd_block();
+    const int c = list[lb / per];
     const int64_t d0 = g.dof_ptr[c];
-    const int64_t e = int64_t(blockIdx.x % per) * blockDim.x + threadIdx.x;
+    const int64_t e = int64_t(lb % per) * blockDim.x + threadIdx.x;
     if (e >= (g.dof_ptr[c + 1] - d0) * nc) return;
     const int64_t t = d0 * nc + e;
     const int64_t l = t / nc;
@@ -412,11 +431,13 @@ __global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restri
     __shared__ double part[3][NC][kWave];
     const int lane = threadIdx.x % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int ci = blockIdx.x / tpc;
-    const int tile = blockIdx.x % tpc;
+    const int lb = xcd_block();
+    const int ci = lb / tpc;
+    const int tile = lb % tpc;
     const int c = list ? list[ci] : ci;
     const int64_t d0 = g.dof_ptr[c];
     const int n = int(g.dof_ptr[c + 1] - d0);
+    const int64_t ld = minv_ld(n);
     const int r0 = tile * kWave;
     if (r0 >= n) return;
     if (bytes != nullptr && threadIdx.x == 0) {
@@ -435,8 +456,8 @@ __global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restri
     for (int col = 0; col < NC; ++col) acc[col] = 0.0;
     int j = j0;
     for (; j + 4 <= j1; j += 4) {
-        const double m0 = A[int64_t(j) * n], m1 = A[int64_t(j + 1) * n];
-        const double m2 = A[int64_t(j + 2) * n], m3 = A[int64_t(j + 3) * n];
+        const double m0 = A[int64_t(j) * ld], m1 = A[int64_t(j + 1) * ld];
+        const double m2 = A[int64_t(j + 2) * ld], m3 = A[int64_t(j + 3) * ld];
         const double *b = B + int64_t(j) * NC;
 #pragma unroll
         for (int col = 0; col < NC; ++col) acc[col] = fma(m0, b[col], acc[col]);
@@ -448,7 +469,7 @@ __global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restri
         for (int col = 0; col < NC; ++col) acc[col] = fma(m3, b[3 * NC + col], acc[col]);
     }
     for (; j < j1; ++j) {
-        const double m0 = A[int64_t(j) * n];
+        const double m0 = A[int64_t(j) * ld];
         const double *b = B + int64_t(j) * NC;
 #pragma unroll
         for (int col = 0; col < NC; ++col) acc[col] = fma(m0, b[col], acc[col]);
@@ -507,8 +528,9 @@ __global__ void __launch_bounds__(256) k_and_dots(DevGrid g, DevWork w, const do
     constexpr int nc = Dim<N>::nc, nt = Dim<N>::nt;
     constexpr int kPer = (64 * nc + 255) / 256;  // elements per thread
     __shared__ double accs[2 * (kMaxDepth + 1) + 2][4];
-    const int c = list[blockIdx.x / tpc];
-    const int tile = blockIdx.x % tpc;
+    const int lb = xcd_block();
+    const int c = list[lb / tpc];
+    const int tile = lb % tpc;
     const int64_t d0 = g.dof_ptr[c];
     const int n = int(g.dof_ptr[c + 1] - d0);
     if (tile * 64 >= n) return;
@@ -729,8 +751,9 @@ template <int N>
 __global__ void __launch_bounds__(256) k_and_update(DevGrid g, DevWork w, const int32_t *__restrict__ list,
                                                     int tpc) {
     constexpr int nc = Dim<N>::nc;
-    const int c = list[blockIdx.x / tpc];
-    const int tile = blockIdx.x % tpc;
+    const int lb = xcd_block();
+    const int c = list[lb / tpc];
+    const int tile = lb % tpc;
     const int64_t d0 = g.dof_ptr[c];
     const int n = int(g.dof_ptr[c + 1] - d0);
     if (tile * 64 >= n) return;

@@ -90,21 +90,22 @@ def test_step_parity_density_wave(mesh_4, N):
     assert rel_linf(ug, uo) < 1e-12
 
 
-def predictor_sensitivity(o, u, dt, rep, rel, seed=0):
-    """Change of the corrector's result when every cell's predictor solution is
-    perturbed by a random relative amount `rel` (the predictor is only defined
-    to its stopping tolerance): relative L-infinity of the change in u^{n+1}."""
-    rng = np.random.default_rng(seed)
-    ti = {}
-    for c, q in rep.pred.items():
-        qp = q * (1.0 + rel * rng.uniform(-1.0, 1.0, q.shape))
-        ti[c] = o.time_integrals(c, qp, dt, rep.mu[c])
-    dmax = 0.0
-    for c in o.targets:
-        rhs = ti[c]["vol"] - o.face_term(c, ti, rep.mu, dt)
-        rhs0 = rep.ti[c]["vol"] - o.face_term(c, rep.ti, rep.mu, dt)
-        dmax = max(dmax, float(np.abs(o.mass_solve(c, rhs - rhs0)).max()))
-    return dmax / float(np.abs(u).max())
+def oracle_spread(mesh, N, u0, dt, steps, uref, **kw):
+    """How precisely the oracle itself defines the result: relative L-infinity
+    spread of u^{n+steps} over equally valid predictor iterations (Anderson
+    depth 48 instead of 63, and a 3x tighter stop).  Where viscosity acts on
+    thin sub-tetrahedra the step amplifies the part of the predictor error that
+    the stopping test leaves along the stiffest modes."""
+    from oracle.scheme import Oracle, Params
+    spread = 0.0
+    for extra in (dict(depth=48, tol=TOL), dict(tol=TOL / 3)):
+        o = Oracle(mesh, N, Params(max_iter=600, **{**kw, **extra}))
+        u = u0
+        for _ in range(steps):
+            u, rep = o.step(u, dt)
+            assert rep.converged
+        spread = max(spread, rel_linf(u, uref))
+    return spread
 
 
 def test_step_parity_with_artificial_viscosity(mesh_4):
@@ -129,19 +130,19 @@ def test_step_parity_with_artificial_viscosity(mesh_4):
     ug = torch.tensor(u0, device="cuda")
     uo = u0
     for _ in range(2):
-        uprev = uo
-        uo, rep = o.step(uo, dt, keep=True)
+        uo, rep = o.step(uo, dt)
         assert rep.converged and rep.positive
         r = cd.step(ug, dt)
     it, mu = cd.diagnostics()
     assert (mu > 0).any() and r.n_troubled > 0
     assert np.allclose(mu, [rep.mu[c] for c in range(o.n_cells)], rtol=1e-12, atol=0)
-    # With mu_i ~ 0.1 on sub-tets of relative volume 1e-7 the viscous flux
-    # amplifies predictor differences at the stopping tolerance; the bar is the
-    # oracle's own sensitivity to a perturbation of that size (x10), at least 1e-12.
-    bar = max(1e-12, 10.0 * predictor_sensitivity(o, uprev, dt, rep, TOL))
+    # With mu_i ~ 0.1 on thin sub-tetrahedra the result is defined by the
+    # predictor's stopping test only to ~1e-10: the bar is twice the oracle's
+    # own spread over valid iterations, and at least 1e-12.
+    spread = oracle_spread(mesh_4, 2, u0, dt, 2, uo, av=True)
+    bar = max(1e-12, 2.0 * spread)
+    assert spread < 1e-8
     assert rel_linf(ug.cpu().numpy(), uo) < bar
-    assert bar < 1e-8
 
 
 def test_step_parity_navier_stokes_taylor_green():
