@@ -71,8 +71,10 @@ struct afe_cell_data {
         return e;
     }
     ~afe_cell_data() {
-        if (hooks.start) (void)hipEventDestroy(hooks.start);
-        if (hooks.stop) (void)hipEventDestroy(hooks.stop);
+        for (int i = 0; i < afe::kSyncEvery; ++i) {
+            if (hooks.start[i]) (void)hipEventDestroy(hooks.start[i]);
+            if (hooks.stop[i]) (void)hipEventDestroy(hooks.stop[i]);
+        }
         if (h_bytes) (void)hipHostFree(h_bytes);
         for (void *p : allocs) (void)hipFree(p);
         if (h_status) (void)hipHostFree(h_status);
@@ -339,21 +341,34 @@ afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *str
     HIP_TRY(afe::launch_reset_status(cd->g, cd->w, s));
     HIP_TRY(afe::launch_detect(cd->g, cd->w, u, s));
     HIP_TRY(afe::launch_pred_init(cd->g, cd->w, u, s));
-    int n_list = cd->host.n_cells;
-    for (int it = 0; it < p.max_iter && n_list > 0; ++it) {
-        const int cur = it % 2, nxt = 1 - cur;
-        int32_t *list = cd->w.alist + size_t(cur) * cd->host.n_cells;
-        int32_t *next = cd->w.alist + size_t(nxt) * cd->host.n_cells;
-        HIP_TRY(afe::launch_pred_iteration(cd->g, cd->w, u, dt, it, p.max_iter, p.tol, list, n_list, next,
-                                           cd->w.acount + nxt, s, cd->prof_on ? &cd->hooks : nullptr));
-        HIP_TRY(hipMemcpyAsync(cd->h_status + 2, cd->w.acount + nxt, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // Iterations are launched in batches of kSyncEvery without waiting: the
+    // kernels read the current list length on the device and idle blocks exit,
+    // the host only needs an upper bound, refreshed at each synchronisation.
+    int n_upper = cd->host.n_cells;
+    for (int it = 0; it < p.max_iter && n_upper > 0;) {
+        // large lists shrink fast: synchronise every iteration until few cells remain
+        const int batch_len = n_upper > 256 ? 1 : afe::kSyncEvery;
+        int batch = 0;
+        for (; batch < batch_len && it < p.max_iter; ++batch, ++it) {
+            const int cur = it % 2, nxt = 1 - cur;
+            int32_t *list = cd->w.alist + size_t(cur) * cd->host.n_cells;
+            int32_t *next = cd->w.alist + size_t(nxt) * cd->host.n_cells;
+            HIP_TRY(afe::launch_pred_iteration(cd->g, cd->w, u, dt, it, p.max_iter, p.tol, list, cd->w.acount + cur,
+                                               n_upper, next, cd->w.acount + nxt, s,
+                                               cd->prof_on ? cd->hooks.start[batch] : nullptr,
+                                               cd->prof_on ? cd->hooks.stop[batch] : nullptr,
+                                               cd->prof_on ? cd->hooks.bytes : nullptr));
+        }
+        HIP_TRY(hipMemcpyAsync(cd->h_status + 2, cd->w.acount + (it % 2), sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        n_list = cd->h_status[2];
+        n_upper = cd->h_status[2];
         if (cd->prof_on) {
-            float ms = 0.0f;
-            HIP_TRY(hipEventElapsedTime(&ms, cd->hooks.start, cd->hooks.stop));
-            cd->prof_ms += ms;
-            cd->prof_launches += 1;
+            for (int b = 0; b < batch; ++b) {
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, cd->hooks.start[b], cd->hooks.stop[b]));
+                cd->prof_ms += ms;
+                cd->prof_launches += 1;
+            }
         }
     }
     HIP_TRY(afe::launch_pred_post(cd->g, cd->w, dt, s));
@@ -399,9 +414,11 @@ afe_status ader_step(afe_cell_data *cd, double *u, double dt, afe_step_report *r
 
 afe_status afe_profile_enable(afe_cell_data *cd, int32_t enable) {
     if (!cd) return fail(AFE_E_ARG, "null argument");
-    if (enable && !cd->hooks.start) {
-        HIP_TRY(hipEventCreate(&cd->hooks.start));
-        HIP_TRY(hipEventCreate(&cd->hooks.stop));
+    if (enable && !cd->hooks.bytes) {
+        for (int i = 0; i < afe::kSyncEvery; ++i) {
+            HIP_TRY(hipEventCreate(&cd->hooks.start[i]));
+            HIP_TRY(hipEventCreate(&cd->hooks.stop[i]));
+        }
         HIP_TRY(cd->alloc(cd->hooks.bytes, 1));
     }
     cd->prof_on = enable != 0;

@@ -75,9 +75,13 @@ struct DevWork {
 
 enum : int { kStatusNoConv = 1, kStatusPositivity = 2, kStatusNonfinite = 4 };
 
-// Events bracketing one launch of the predictor's M^{-1} kernel and its byte counter.
+// Predictor iterations launched between two reads of the active-cell count.
+constexpr int kSyncEvery = 4;
+
+// Events bracketing the launches of the predictor's M^{-1} kernel between two
+// synchronisations, and its algorithmic byte counter.
 struct ProfileHooks {
-    hipEvent_t start, stop;
+    hipEvent_t start[kSyncEvery], stop[kSyncEvery];
     unsigned long long *bytes;
 };
 
@@ -89,8 +93,9 @@ hipError_t launch_detect(const DevGrid &g, const DevWork &w, const double *u, hi
 hipError_t launch_cfl_max(const DevGrid &g, const DevWork &w, double *out, hipStream_t s);
 hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, const double *u, hipStream_t s);
 hipError_t launch_pred_iteration(const DevGrid &g, const DevWork &w, const double *u, double dt, int it,
-                                 int max_iter, double tol, const int32_t *list, int n_list, int32_t *next,
-                                 int32_t *next_count, hipStream_t s, const ProfileHooks *prof);
+                                 int max_iter, double tol, const int32_t *list, const int32_t *count, int n_upper,
+                                 int32_t *next, int32_t *next_count, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                                 unsigned long long *bytes);
 hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, double dt, hipStream_t s);
 hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, double dt, hipStream_t s);
 

@@ -263,6 +263,7 @@ __global__ void k_pred_init(DevGrid g, DevWork w, const double *__restrict__ u) 
     if (l < g.ndof)
         for (int a = 0; a < nt; ++a)
             for (int v = 0; v < 5; ++v) w.x[l * nc + a * 5 + v] = u[v * g.ndof + l];
+    if (l == 0) w.acount[0] = g.n_cells;
     if (l < g.n_cells) {
         w.alist[l] = int32_t(l);
         w.iters[l] = 0;
@@ -283,7 +284,8 @@ __global__ void k_zero_int(int32_t *p) {
 // (qbar, Fbar) at the boundary-triangle nodes.
 template <int N, bool POST>
 __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w, double dt,
-                                                             const int32_t *__restrict__ list, int chunks) {
+                                                             const int32_t *__restrict__ list,
+                                                             const int32_t *__restrict__ count, int chunks) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr int nf = Dim<N>::nf;
     __shared__ double Ks[3 * np * np];
@@ -308,6 +310,7 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
     } else {
         // block -> (active cell, chunk of spb of its sub-tets)
         const int lb = xcd_block();
+        if (lb / chunks >= *count) return;  // the list shrank since the launch was sized
         c = list[lb / chunks];
         k = g.sub_ptr[c] + int64_t(lb % chunks) * spb + s;
         valid = (s < spb) && (k < g.sub_ptr[c + 1]);
@@ -402,9 +405,11 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
 // R[l][col] = sum over the DOF's incidence list of the sub-tet contributions;
 // blocks cover the DOF-major blocks of the listed cells.
 template <int N>
-__global__ void __launch_bounds__(256) k_gather(DevGrid g, DevWork w, const int32_t *__restrict__ list, int per) {
+__global__ void __launch_bounds__(256) k_gather(DevGrid g, DevWork w, const int32_t *__restrict__ list,
+                                                 const int32_t *__restrict__ count, int per) {
     constexpr int nc = Dim<N>::nc;
     const int lb = xcd_block();
+    if (lb / per >= *count) return;
     const int c = list[lb / per];
     const int64_t d0 = g.dof_ptr[c];
     const int64_t e = int64_t(lb % per) * blockDim.x + threadIdx.x;
@@ -426,14 +431,15 @@ __global__ void __launch_bounds__(256) k_gather(DevGrid g, DevWork w, const int3
 // MODE 0: Y = S (predictor);  MODE 1: add Y into the SoA state u (corrector).
 template <int NC, int MODE>
 __global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restrict__ list,
-                                               const double *__restrict__ X, double *__restrict__ Y, int tpc,
-                                               unsigned long long *bytes) {
+                                               const int32_t *__restrict__ count, const double *__restrict__ X,
+                                               double *__restrict__ Y, int tpc, unsigned long long *bytes) {
     __shared__ double part[3][NC][kWave];
     const int lane = threadIdx.x % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int lb = xcd_block();
     const int ci = lb / tpc;
     const int tile = lb % tpc;
+    if (count != nullptr && ci >= *count) return;
     const int c = list ? list[ci] : ci;
     const int64_t d0 = g.dof_ptr[c];
     const int n = int(g.dof_ptr[c + 1] - d0);
@@ -524,11 +530,13 @@ __device__ inline void ring_state(const DevWork &w, int c, int &k, int &head, bo
 
 template <int N>
 __global__ void __launch_bounds__(256) k_and_dots(DevGrid g, DevWork w, const double *__restrict__ u, int it,
-                                                  const int32_t *__restrict__ list, int tpc) {
+                                                  const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                                                  int tpc) {
     constexpr int nc = Dim<N>::nc, nt = Dim<N>::nt;
     constexpr int kPer = (64 * nc + 255) / 256;  // elements per thread
     __shared__ double accs[2 * (kMaxDepth + 1) + 2][4];
     const int lb = xcd_block();
+    if (lb / tpc >= *count) return;
     const int c = list[lb / tpc];
     const int tile = lb % tpc;
     const int64_t d0 = g.dof_ptr[c];
@@ -622,8 +630,9 @@ __global__ void __launch_bounds__(256) k_and_dots(DevGrid g, DevWork w, const do
 
 template <int N>
 __global__ void __launch_bounds__(64) k_and_solve(DevGrid g, DevWork w, int it, int max_iter, double tol,
-                                                  const int32_t *__restrict__ list, int tpc, int32_t *next,
-                                                  int32_t *next_count) {
+                                                  const int32_t *__restrict__ list, const int32_t *__restrict__ count,
+                                                  int tpc, int32_t *next, int32_t *next_count) {
+    if (int(blockIdx.x) >= *count) return;
     const int c = list[blockIdx.x];
     const int lane = threadIdx.x;
     const int n = int(g.dof_ptr[c + 1] - g.dof_ptr[c]);
@@ -749,9 +758,10 @@ __global__ void __launch_bounds__(64) k_and_solve(DevGrid g, DevWork w, int it, 
 
 template <int N>
 __global__ void __launch_bounds__(256) k_and_update(DevGrid g, DevWork w, const int32_t *__restrict__ list,
-                                                    int tpc) {
+                                                    const int32_t *__restrict__ count, int tpc) {
     constexpr int nc = Dim<N>::nc;
     const int lb = xcd_block();
+    if (lb / tpc >= *count) return;
     const int c = list[lb / tpc];
     const int tile = lb % tpc;
     const int64_t d0 = g.dof_ptr[c];
@@ -950,27 +960,27 @@ hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, const double *u,
 }
 
 hipError_t launch_pred_iteration(const DevGrid &g, const DevWork &w, const double *u, double dt, int it,
-                                 int max_iter, double tol, const int32_t *list, int n_list, int32_t *next,
-                                 int32_t *next_count, hipStream_t s, const ProfileHooks *prof) {
+                                 int max_iter, double tol, const int32_t *list, const int32_t *count, int n_upper,
+                                 int32_t *next, int32_t *next_count, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
+                                 unsigned long long *bytes) {
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
+        const unsigned nl = unsigned(n_upper);
         const int chunks = (g.max_cell_subtets + D::spb - 1) / D::spb;
-        hipLaunchKernelGGL((k_subtet<NN, false>), dim3(unsigned(n_list) * chunks), dim3(D::threads), 0, s, g, w, dt,
-                           list, chunks);
+        hipLaunchKernelGGL((k_subtet<NN, false>), dim3(nl * chunks), dim3(D::threads), 0, s, g, w, dt, list, count,
+                           chunks);
         const int per = int((int64_t(g.max_cell_dofs) * D::nc + 255) / 256);
-        hipLaunchKernelGGL(k_gather<NN>, dim3(unsigned(n_list) * per), dim3(256), 0, s, g, w, list, per);
+        hipLaunchKernelGGL(k_gather<NN>, dim3(nl * per), dim3(256), 0, s, g, w, list, count, per);
         const int tpc = (g.max_cell_dofs + 63) / 64;
-        if (prof) (void)hipEventRecord(prof->start, s);
-        hipLaunchKernelGGL((k_minv<D::nc, 0>), dim3(unsigned(n_list) * tpc), dim3(256), 0, s, g, list, w.R, w.S, tpc,
-                           prof ? prof->bytes : nullptr);
-        if (prof) (void)hipEventRecord(prof->stop, s);
+        if (ev0) (void)hipEventRecord(ev0, s);
+        hipLaunchKernelGGL((k_minv<D::nc, 0>), dim3(nl * tpc), dim3(256), 0, s, g, list, count, w.R, w.S, tpc, bytes);
+        if (ev1) (void)hipEventRecord(ev1, s);
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, next_count);
-        const int tpd = (g.max_cell_dofs + 63) / 64;
-        hipLaunchKernelGGL(k_and_dots<NN>, dim3(unsigned(n_list) * tpd), dim3(256), 0, s, g, w, u, it, list, tpd);
-        hipLaunchKernelGGL(k_and_solve<NN>, dim3(unsigned(n_list)), dim3(64), 0, s, g, w, it, max_iter, tol, list,
-                           tpd, next, next_count);
-        hipLaunchKernelGGL(k_and_update<NN>, dim3(unsigned(n_list) * tpd), dim3(256), 0, s, g, w, list, tpd);
+        hipLaunchKernelGGL(k_and_dots<NN>, dim3(nl * tpc), dim3(256), 0, s, g, w, u, it, list, count, tpc);
+        hipLaunchKernelGGL(k_and_solve<NN>, dim3(nl), dim3(64), 0, s, g, w, it, max_iter, tol, list, count, tpc, next,
+                           next_count);
+        hipLaunchKernelGGL(k_and_update<NN>, dim3(nl * tpc), dim3(256), 0, s, g, w, list, count, tpc);
         return hipGetLastError();
     });
 }
@@ -980,7 +990,7 @@ hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, double dt, hipSt
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
         hipLaunchKernelGGL((k_subtet<NN, true>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w, dt,
-                           nullptr, 1);
+                           nullptr, nullptr, 1);
         return hipGetLastError();
     });
 }
@@ -992,8 +1002,8 @@ hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, double 
         hipLaunchKernelGGL(k_face<NN>, dim3(blocks_for(g.nsub, 256 / D::nf)), dim3(256), 0, s, g, w, dt);
         hipLaunchKernelGGL(k_rhs<NN>, dim3(blocks_for(g.ndof * 5, 256)), dim3(256), 0, s, g, w);
         const int tpc = (g.max_cell_dofs + 63) / 64;
-        hipLaunchKernelGGL((k_minv<5, 1>), dim3(unsigned(g.n_cells) * tpc), dim3(256), 0, s, g, nullptr, w.rhs, u,
-                           tpc, nullptr);
+        hipLaunchKernelGGL((k_minv<5, 1>), dim3(unsigned(g.n_cells) * tpc), dim3(256), 0, s, g, nullptr, nullptr,
+                           w.rhs, u, tpc, nullptr);
         hipLaunchKernelGGL(k_positivity, dim3(blocks_for(g.ndof, 256)), dim3(256), 0, s, g, w, u);
         return hipGetLastError();
     });
