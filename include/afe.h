@@ -75,7 +75,9 @@ typedef struct {
     int32_t max_iter;    /* predictor iteration cap                                 */
     double tol;          /* predictor stop: max|G(q)-q| <= tol * max(1, max|G(q)|)  */
     int32_t accel_depth; /* Anderson depth m of the predictor iteration (0 = plain)  */
-    int32_t precision;   /* AFE_FP64 (AFE_MIXED is rejected by this version)        */
+    int32_t precision;   /* AFE_FP64; AFE_MIXED: the predictor iterates with an FP32  */
+                         /* Jacobi-scaled copy of M_i^{-1} as preconditioner of the   */
+                         /* FP64 residual of eq:ADER-localCauchy (same fixed point)   */
     size_t hbm_budget;   /* bytes of device memory the object may use (0 = no cap)  */
 } afe_params;
 

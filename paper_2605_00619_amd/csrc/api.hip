@@ -84,12 +84,13 @@ struct afe_cell_data {
 
 namespace {
 
-size_t estimate_bytes(const afe::HostGrid &h, int depth) {
+size_t estimate_bytes(const afe::HostGrid &h, int depth, bool mixed) {
     const size_t nc = size_t(5) * (h.N + 1);
     size_t b = 0;
     for (int c = 0; c < h.n_cells; ++c) {
         size_t n = size_t(h.dof_ptr[c + 1] - h.dof_ptr[c]);
         b += n * ((n + 15) & ~size_t(15)) * sizeof(double);
+        if (mixed) b += n * ((n + 31) & ~size_t(31)) * sizeof(float);
     }
     b += size_t(h.ndof) * nc * sizeof(double) * (5 + 2 * size_t(std::max(depth, 1)));
     b += size_t(h.n_cells) * ((h.max_cell_dofs + 63) / 64) * 130 * sizeof(double);
@@ -113,7 +114,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
                                afe_cell_data **out) {
     if (!mesh || !params || !out) return fail(AFE_E_ARG, "null argument");
     *out = nullptr;
-    if (params->precision != AFE_FP64) return fail(AFE_E_ARG, "only AFE_FP64 is implemented");
+    if (params->precision != AFE_FP64 && params->precision != AFE_MIXED) return fail(AFE_E_ARG, "unknown precision");
     if (params->accel_depth < 0 || params->accel_depth > 63) return fail(AFE_E_ARG, "accel_depth must be in [0, 63]");
     if (params->max_iter < 1) return fail(AFE_E_ARG, "max_iter must be >= 1");
     if (!(params->gamma > 1.0) || params->mu < 0.0 || !(params->tol >= 0.0))
@@ -130,7 +131,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     cd->params = *params;
     const afe::HostGrid &h = cd->host;
     const int depth = params->accel_depth;
-    size_t need = estimate_bytes(h, depth);
+    size_t need = estimate_bytes(h, depth, params->precision == AFE_MIXED);
     if (params->hbm_budget > 0 && need > params->hbm_budget) {
         delete cd;
         return fail(AFE_E_HBM_BUDGET, "needs " + std::to_string(need) + " bytes, budget " +
@@ -152,15 +153,18 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     g.mu = params->mu;
     g.m1 = params->m1;
     g.av = params->av;
-    std::vector<int64_t> minv_ptr(h.n_cells + 1, 0);
+    g.mixed = params->precision == AFE_MIXED ? 1 : 0;
+    std::vector<int64_t> minv_ptr(h.n_cells + 1, 0), minv32_ptr(h.n_cells + 1, 0);
     for (int c = 0; c < h.n_cells; ++c) {
         int64_t n = h.dof_ptr[c + 1] - h.dof_ptr[c];
         minv_ptr[c + 1] = minv_ptr[c] + n * ((n + 15) & ~int64_t(15));  // rows padded to 128 bytes
+        minv32_ptr[c + 1] = minv32_ptr[c] + (g.mixed ? n * ((n + 31) & ~int64_t(31)) : 0);
     }
     hipError_t e;
     if ((e = cd->upload(g.dof_ptr, h.dof_ptr, s)) != hipSuccess ||
         (e = cd->upload(g.sub_ptr, h.sub_ptr, s)) != hipSuccess ||
         (e = cd->upload(g.minv_ptr, minv_ptr, s)) != hipSuccess ||
+        (e = cd->upload(g.minv32_ptr, minv32_ptr, s)) != hipSuccess ||
         (e = cd->upload(g.conn, h.conn, s)) != hipSuccess ||
         (e = cd->upload(g.sub_cell, h.sub_cell, s)) != hipSuccess ||
         (e = cd->upload(g.geo, h.geo, s)) != hipSuccess ||
@@ -195,7 +199,10 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         ref.fn[j] = R.face_nodes[j];
     }
     for (int a = 0; a < R.nt; ++a) ref.w[a] = R.w[a];
-    for (int i = 0; i < R.nt * R.nt; ++i) ref.Ktau_inv[i] = R.Ktau_inv[i];
+    for (int i = 0; i < R.nt * R.nt; ++i) {
+        ref.Ktau_inv[i] = R.Ktau_inv[i];
+        ref.Ktau[i] = R.Ktau[i];
+    }
     afe::DevRef *dref = nullptr;
     if ((e = cd->alloc(dref, 1)) != hipSuccess || (e = hipMemcpyAsync(dref, &ref, sizeof(ref), hipMemcpyHostToDevice, s)) != hipSuccess) {
         std::string m = hipGetErrorString(e);
@@ -208,6 +215,9 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     const int dslots = std::max(depth, 1);
     w.depth = depth;
     if ((e = cd->alloc(g.minv, size_t(minv_ptr[h.n_cells]))) != hipSuccess ||
+        (e = cd->alloc(g.dscale, nd)) != hipSuccess ||
+        (e = cd->alloc(g.minv32, size_t(minv32_ptr[h.n_cells]))) != hipSuccess ||
+        (e = cd->alloc(w.R32, g.mixed ? nd * nc : 1)) != hipSuccess ||
         (e = cd->alloc(w.x, nd * nc)) != hipSuccess || (e = cd->alloc(w.R, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.S, nd * nc)) != hipSuccess || (e = cd->alloc(w.fprev, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.gprev, nd * nc)) != hipSuccess || 

@@ -15,6 +15,7 @@ struct DevRef {
     double zsum[10];         // int_tri phi_j = sum_i Z[i][j]
     double w[4];             // Gauss-Legendre weights on [0, 1]
     double Ktau_inv[16];     // inverse of the upwind time operator
+    double Ktau[16];         // upwind time operator psi_a(1) psi_b(1) - int psi_a' psi_b
     int fn[10];              // face node -> reference node
 };
 
@@ -25,6 +26,7 @@ struct DevGrid {
     int max_cell_dofs, max_cell_subtets;
     double gamma, mu, m1;
     int av;
+    int mixed;                // 1: FP32 preconditioner for the predictor iteration
     // connectivity and geometry
     const int64_t *dof_ptr;   // [n_cells + 1]
     const int64_t *sub_ptr;   // [n_cells + 1]
@@ -41,13 +43,17 @@ struct DevGrid {
     const int32_t *inc_ptr, *inc_idx;
     const int32_t *finc_ptr, *finc_idx;
     const DevRef *ref;
-    double *minv;             // dense M_i^{-1}, row-major, symmetric
+    double *minv;             // dense M_i^{-1}, row-major, symmetric, rows padded to 16
+    double *dscale;           // [ndof] Jacobi scales diag(M_i)^{-1/2}
+    float *minv32;            // mixed: FP32 scaled inverse, rows padded to 32
+    const int64_t *minv32_ptr;
 };
 
 // Work buffers of the predictor / corrector.
 struct DevWork {
     double *x;       // [ndof][nc] current predictor iterate (final: the solution)
-    double *R;       // [ndof][nc] assembled stiffness term
+    double *R;       // [ndof][nc] assembled stiffness term (FP64 path)
+    float *R32;      // [ndof][nc] mixed: scaled FP32 residual
     double *S;       // [ndof][nc] M^{-1} R
     double *rk;      // [nsub][np][nc] per-sub-tet contributions
     double *fprev;   // [ndof][nc] residual G(x) - x of the current iterate

@@ -127,7 +127,10 @@ __global__ void __launch_bounds__(1024) k_mass_invert(DevGrid g) {
     double *colk = sh + 2 * n;
     const int tid = threadIdx.x, nth = blockDim.x;
     const int tx = tid % 64, ty = tid / 64, ny = nth / 64;
-    for (int i = tid; i < n; i += nth) dsc[i] = 1.0 / sqrt(A[int64_t(i) * ld + i]);
+    for (int i = tid; i < n; i += nth) {
+        dsc[i] = 1.0 / sqrt(A[int64_t(i) * ld + i]);
+        g.dscale[g.dof_ptr[c] + i] = dsc[i];
+    }
     __syncthreads();
     for (int i = ty; i < n; i += ny)
         for (int j = tx; j < n; j += 64) A[int64_t(i) * ld + j] *= dsc[i] * dsc[j];
@@ -158,6 +161,23 @@ __global__ void __launch_bounds__(1024) k_mass_invert(DevGrid g) {
             A[int64_t(i) * ld + j] = v;
             A[int64_t(j) * ld + i] = v;
         }
+}
+
+// FP32 copy of the Jacobi-scaled inverse: M_i^{-1} = D A D with D = diag(M_i)^{-1/2};
+// A (entries O(1), condition ~17) is stored in FP32, D stays FP64.
+__device__ __host__ inline int64_t minv32_ld(int64_t n) { return (n + 31) & ~int64_t(31); }
+
+__global__ void __launch_bounds__(256) k_minv_to_f32(DevGrid g) {
+    const int c = blockIdx.x;
+    const int64_t d0 = g.dof_ptr[c];
+    const int64_t n = g.dof_ptr[c + 1] - d0;
+    const int64_t ld = minv_ld(n), ld32 = minv32_ld(n);
+    const double *A = g.minv + g.minv_ptr[c];
+    float *B = g.minv32 + g.minv32_ptr[c];
+    for (int64_t e = threadIdx.x; e < n * ld32; e += blockDim.x) {
+        const int64_t i = e / ld32, j = e % ld32;
+        B[e] = j < n ? float(A[i * ld + j] / (g.dscale[d0 + i] * g.dscale[d0 + j])) : 0.0f;
+    }
 }
 
 __global__ void k_prim_to_cons(int64_t ndof, double gamma, const double *prim, double *u) {
@@ -285,7 +305,8 @@ __global__ void k_zero_int(int32_t *p) {
 template <int N, bool POST>
 __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w, double dt,
                                                              const int32_t *__restrict__ list,
-                                                             const int32_t *__restrict__ count, int chunks) {
+                                                             const int32_t *__restrict__ count, int chunks,
+                                                             const double *__restrict__ u) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr int nf = Dim<N>::nf;
     __shared__ double Ks[3 * np * np];
@@ -294,7 +315,14 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
     __shared__ double fs[spb][nt][np][15];
     __shared__ double Fs[POST ? spb : 1][POST ? nt : 1][POST ? np : 1][15];
     __shared__ double fbar[POST ? spb : 1][POST ? np : 1][15];
+    // mixed precision: u^n at the sub-tet nodes and M^ for the mass term
+    __shared__ double us[POST ? 1 : spb][POST ? 1 : np][5];
+    __shared__ double Ms[POST ? 1 : np * np];
+    __shared__ double mt[POST ? 1 : spb][POST ? 1 : nt][POST ? 1 : np][5];  // M^ (q_b - u^n) per time node
     const int tid = threadIdx.x;
+    const bool mixed = !POST && g.mixed;
+    if (mixed)
+        for (int t = tid; t < np * np; t += blockDim.x) Ms[POST ? 0 : t] = g.ref->M[t];
     for (int t = tid; t < 3 * np * np; t += blockDim.x) {
         Ks[t] = g.ref->K[t];
         Ds[t] = g.ref->D[t];
@@ -326,6 +354,8 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
             q[v] = w.x[l * nc + a * 5 + v];
             qs[s][a][m][v] = q[v];
         }
+        if (mixed && a == 0)
+            for (int v = 0; v < 5; ++v) us[POST ? 0 : s][POST ? 0 : m][v] = u[v * g.ndof + l];
     }
     __syncthreads();
     if (valid) {
@@ -349,6 +379,17 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
             for (int x = 0; x < 3; ++x)
                 for (int v = 0; v < 5; ++v) Fs[POST ? s : 0][POST ? a : 0][POST ? m : 0][x * 5 + v] = F[x][v];
     }
+    if (mixed) {
+        __syncthreads();
+        // thread (s, b = a, m): the sub-tet mass product of time node b
+        double t[5] = {0, 0, 0, 0, 0};
+        if (valid)
+            for (int p = 0; p < np; ++p) {
+                const double mm = Ms[POST ? 0 : m * np + p];
+                for (int v = 0; v < 5; ++v) t[v] += mm * (qs[s][a][p][v] - us[POST ? 0 : s][POST ? 0 : p][v]);
+            }
+        for (int v = 0; v < 5; ++v) mt[POST ? 0 : s][POST ? 0 : a][POST ? 0 : m][v] = t[v];
+    }
     __syncthreads();
     if (!POST) {
         if (!valid) return;
@@ -360,7 +401,18 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
             }
         const double sc = g.ref->w[a] * dj;
         double *out = w.rk + (k * np + m) * nc + a * 5;
-        for (int v = 0; v < 5; ++v) out[v] = sc * r[v];
+        if (mixed) {
+            // unpreconditioned residual of eq:ADER-localCauchy: add the sub-tet's part
+            // of (K_tau (x) M_i)(q - 1 (x) u^n)
+            double mr[5] = {0, 0, 0, 0, 0};
+            for (int b = 0; b < nt; ++b) {
+                const double kt = g.ref->Ktau[a * nt + b];
+                for (int v = 0; v < 5; ++v) mr[v] += kt * mt[POST ? 0 : s][POST ? 0 : b][POST ? 0 : m][v];
+            }
+            for (int v = 0; v < 5; ++v) out[v] = sc * r[v] + dj * mr[v];
+        } else {
+            for (int v = 0; v < 5; ++v) out[v] = sc * r[v];
+        }
         return;
     }
     // POST: time integrals
@@ -419,7 +471,10 @@ __global__ void __launch_bounds__(256) k_gather(DevGrid g, DevWork w, const int3
     const int col = int(t % nc);
     double acc = 0.0;
     for (int q = g.inc_ptr[l]; q < g.inc_ptr[l + 1]; ++q) acc += w.rk[int64_t(g.inc_idx[q]) * nc + col];
-    w.R[t] = acc;
+    if (g.mixed)
+        w.R32[t] = float(acc * g.dscale[l]);
+    else
+        w.R[t] = acc;
 }
 
 // Y = M_i^{-1} X for the listed cells (list == nullptr: all cells), X and Y
@@ -493,6 +548,75 @@ __global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restri
                 Y[(d0 + row) * NC + col] = v;
             else
                 Y[col * g.ndof + d0 + row] += v;
+        }
+    }
+}
+
+// Mixed precision: S = D (A32 (D R)) with the FP32 scaled inverse A32 and the
+// FP32 right-hand side X32 = D R (written by the gather); FP32 accumulation,
+// result scaled back to FP64.  Same tiling as k_minv.
+template <int NC>
+__global__ void __launch_bounds__(256) k_minv_f32(DevGrid g, const int32_t *__restrict__ list,
+                                                   const int32_t *__restrict__ count, const float *__restrict__ X,
+                                                   double *__restrict__ Y, int tpc, unsigned long long *bytes) {
+    __shared__ float part[3][NC][kWave];
+    const int lane = threadIdx.x % kWave;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    const int lb = xcd_block();
+    const int ci = lb / tpc;
+    const int tile = lb % tpc;
+    if (ci >= *count) return;
+    const int c = list[ci];
+    const int64_t d0 = g.dof_ptr[c];
+    const int n = int(g.dof_ptr[c + 1] - d0);
+    const int64_t ld = minv32_ld(n);
+    const int r0 = tile * kWave;
+    if (r0 >= n) return;
+    if (bytes != nullptr && threadIdx.x == 0) {
+        const unsigned long long rows = unsigned(min(kWave, n - r0));
+        atomicAdd(bytes, 4ull * rows * unsigned(n) + 8ull * rows * NC + (tile == 0 ? 4ull * unsigned(n) * NC : 0ull));
+    }
+    const int row = r0 + lane;
+    const bool ok = row < n;
+    const int rowc = ok ? row : n - 1;
+    const float *__restrict__ A = g.minv32 + g.minv32_ptr[c] + rowc;
+    const float *__restrict__ B = X + d0 * NC;
+    const int span = (n + 3) / 4;
+    const int j0 = min(n, wv * span), j1 = min(n, j0 + span);
+    float acc[NC];
+#pragma unroll
+    for (int col = 0; col < NC; ++col) acc[col] = 0.0f;
+    int j = j0;
+    for (; j + 4 <= j1; j += 4) {
+        const float m0 = A[int64_t(j) * ld], m1 = A[int64_t(j + 1) * ld];
+        const float m2 = A[int64_t(j + 2) * ld], m3 = A[int64_t(j + 3) * ld];
+        const float *b = B + int64_t(j) * NC;
+#pragma unroll
+        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m0, b[col], acc[col]);
+#pragma unroll
+        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m1, b[NC + col], acc[col]);
+#pragma unroll
+        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m2, b[2 * NC + col], acc[col]);
+#pragma unroll
+        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m3, b[3 * NC + col], acc[col]);
+    }
+    for (; j < j1; ++j) {
+        const float m0 = A[int64_t(j) * ld];
+        const float *b = B + int64_t(j) * NC;
+#pragma unroll
+        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m0, b[col], acc[col]);
+    }
+    if (wv > 0) {
+#pragma unroll
+        for (int col = 0; col < NC; ++col) part[wv - 1][col][lane] = acc[col];
+    }
+    __syncthreads();
+    if (wv == 0 && ok) {
+        const double sc = g.dscale[d0 + row];
+#pragma unroll
+        for (int col = 0; col < NC; ++col) {
+            const float v = ((acc[col] + part[0][col][lane]) + part[1][col][lane]) + part[2][col][lane];
+            Y[(d0 + row) * NC + col] = sc * double(v);
         }
     }
 }
@@ -571,8 +695,10 @@ __global__ void __launch_bounds__(256) k_and_dots(DevGrid g, DevWork w, const do
             double acc = 0.0;
 #pragma unroll
             for (int a = 0; a < nt; ++a) acc += g.ref->Ktau_inv[b * nt + a] * sr[a * 5];
-            const double gv = u[v * g.ndof + d0 + l] - acc;
-            const double fv = gv - w.x[base + e];
+            const double xv = w.x[base + e];
+            // FP64: G = u^n - ..., mixed: G = x - ... with S from the residual
+            const double gv = (g.mixed ? xv : u[v * g.ndof + d0 + l]) - acc;
+            const double fv = gv - xv;
             fmx = fmax(fmx, fabs(fv));
             gmx = fmax(gmx, fabs(gv));
             if (hist_on) {
@@ -931,6 +1057,7 @@ hipError_t launch_mass_assemble(const DevGrid &g, hipStream_t s) {
 hipError_t launch_mass_invert(const DevGrid &g, hipStream_t s) {
     size_t shmem = size_t(3) * g.max_cell_dofs * sizeof(double);
     hipLaunchKernelGGL(k_mass_invert, dim3(g.n_cells), dim3(1024), shmem, s, g);
+    if (g.mixed) hipLaunchKernelGGL(k_minv_to_f32, dim3(g.n_cells), dim3(256), 0, s, g);
     return hipGetLastError();
 }
 
@@ -969,12 +1096,17 @@ hipError_t launch_pred_iteration(const DevGrid &g, const DevWork &w, const doubl
         const unsigned nl = unsigned(n_upper);
         const int chunks = (g.max_cell_subtets + D::spb - 1) / D::spb;
         hipLaunchKernelGGL((k_subtet<NN, false>), dim3(nl * chunks), dim3(D::threads), 0, s, g, w, dt, list, count,
-                           chunks);
+                           chunks, u);
         const int per = int((int64_t(g.max_cell_dofs) * D::nc + 255) / 256);
         hipLaunchKernelGGL(k_gather<NN>, dim3(nl * per), dim3(256), 0, s, g, w, list, count, per);
         const int tpc = (g.max_cell_dofs + 63) / 64;
         if (ev0) (void)hipEventRecord(ev0, s);
-        hipLaunchKernelGGL((k_minv<D::nc, 0>), dim3(nl * tpc), dim3(256), 0, s, g, list, count, w.R, w.S, tpc, bytes);
+        if (g.mixed)
+            hipLaunchKernelGGL((k_minv_f32<D::nc>), dim3(nl * tpc), dim3(256), 0, s, g, list, count, w.R32, w.S, tpc,
+                               bytes);
+        else
+            hipLaunchKernelGGL((k_minv<D::nc, 0>), dim3(nl * tpc), dim3(256), 0, s, g, list, count, w.R, w.S, tpc,
+                               bytes);
         if (ev1) (void)hipEventRecord(ev1, s);
         hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, next_count);
         hipLaunchKernelGGL(k_and_dots<NN>, dim3(nl * tpc), dim3(256), 0, s, g, w, u, it, list, count, tpc);
@@ -990,7 +1122,7 @@ hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, double dt, hipSt
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
         hipLaunchKernelGGL((k_subtet<NN, true>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w, dt,
-                           nullptr, nullptr, 1);
+                           nullptr, nullptr, 1, nullptr);
         return hipGetLastError();
     });
 }

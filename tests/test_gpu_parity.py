@@ -198,3 +198,16 @@ def test_failure_statuses(mesh_4):
     with pytest.raises(afe.AfeError) as e:
         cd.step(ug, 1e-4)
     assert e.value.name == "AFE_E_POSITIVITY"
+
+
+@pytest.mark.parametrize("N", [2, 3])
+def test_mixed_precision_reaches_the_fp64_fixed_point(mesh_4, N):
+    """AFE_MIXED iterates with an FP32 M_i^-1 as preconditioner of the FP64
+    residual of eq:ADER-localCauchy, so the step converges to the same fixed
+    point: the state matches the FP64 oracle to the same bar."""
+    from oracle.scheme import Params
+    afe = _lib()
+    steps = 2 if N < 3 else 1
+    uo, ug, reps, cd, o, dt = _run_both(mesh_4, N, density_wave, steps, 0.004, Params(),
+                                        afe.Params(precision=afe.AFE_MIXED))
+    assert rel_linf(ug, uo) < 1e-12
