@@ -45,20 +45,77 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str, achieved_bytes_per_launch: float):
-    """HBM bytes per launch of the dominant kernel from committed counter runs
-    (profiles/traffic_<workload>.json), only if taken on the current kernels."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+def dominant_kernel(precision: str, N: int) -> str:
+    nc = 5 * (N + 1)
+    return f"k_minv<{nc}, 0>" if precision == "fp64" else f"k_minv_f32<{nc}>"
+
+
+def traffic_path(workload: str, precision: str) -> str:
+    return os.path.join(ROOT, "profiles", f"traffic_{workload}_{precision}.json")
+
+
+def measured_traffic(workload: str, precision: str, algorithmic_bytes_per_launch: float):
+    """HBM bytes per launch of the dominant kernel: the ratio of counted to
+    algorithmic bytes from committed counter runs, times this run's algorithmic
+    bytes per launch; None unless the counters were taken on the current kernels."""
+    path = traffic_path(workload, precision)
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel_source_hash") != kernel_source_hash():
         return None
-    return rec.get("hbm_bytes_per_launch")
+    return rec["hbm_over_algorithmic"] * algorithmic_bytes_per_launch
 
 
-def cpu_baseline(mesh, N, u0_np, dt, budget_s: float = 20.0, cluster_size: int = 48):
+def summarize_counters(fetch_dir: str, write_dir: str) -> int:
+    """Turn two rocprofv3 --pmc runs of this script (FETCH_SIZE, then
+    WRITE_SIZE, each with --copy-probe-mib and its JSON line saved as
+    bench.json in the output folder) into profiles/traffic_<workload>_<precision>.json.
+
+    Each counter is calibrated on the plain 1 GiB device copy the run makes
+    first (the largest __amd_rocclr_copyBuffer dispatch): factor = true bytes /
+    counted bytes.  The dominant kernel's counted bytes, summed over its
+    dispatches and scaled, are divided by the algorithmic bytes the library
+    counted for the same dispatches."""
+    import csv
+
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        with open(os.path.join(d, "bench.json")) as fh:
+            b = json.loads(fh.read().strip().splitlines()[-1])
+        wl = b["config"]["name"]
+        prec = "fp64" if b["dtype"] == "f64" else "mixed"
+        name = dominant_kernel(prec, b["config"]["N"])
+        copy_kib, kib, n = 0.0, 0.0, 0
+        with open(os.path.join(d, "run_counter_collection.csv")) as fh:
+            for r in csv.DictReader(fh):
+                if r["Counter_Name"] != counter:
+                    continue
+                v = float(r["Counter_Value"])
+                if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer"):
+                    copy_kib = max(copy_kib, v)
+                elif name in r["Kernel_Name"]:
+                    kib += v
+                    n += 1
+        true_kib = b["copy_probe_bytes"] / 1024.0
+        factor = true_kib / copy_kib
+        if n != b["roofline"]["launches"]:
+            raise RuntimeError(f"{counter}: {n} dispatches of {name} counted, {b['roofline']['launches']} timed")
+        alg = b["roofline"]["algorithmic_bytes_per_launch"] * n
+        out[counter] = dict(counted_kib=kib, dispatches=n, copy_factor=factor,
+                            bytes=kib * 1024.0 * factor, algorithmic_bytes=alg)
+    rec = dict(workload=wl, precision=prec, kernel=name, kernel_source_hash=kernel_source_hash(),
+               counters=out,
+               hbm_over_algorithmic=sum(v["bytes"] for v in out.values()) / out["FETCH_SIZE"]["algorithmic_bytes"])
+    with open(traffic_path(wl, prec), "w") as fh:
+        json.dump(rec, fh, indent=1)
+        fh.write("\n")
+    print(json.dumps(rec))
+    return 0
+
+
+def cpu_baseline(mesh, N, u0_np, dt, budget_s: float = 20.0, cluster_size: int = 120):
     """Time the CPU oracle on a bounded sample of the same workload and
     extrapolate its full-step DOF-updates/s: predictor + time integrals on a
     cluster of cells (breadth-first from cell 0) and their neighbours, the
@@ -130,7 +187,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic record from two counter runs and exit")
     args = ap.parse_args()
+    if args.summarize_counters:
+        return summarize_counters(*args.summarize_counters)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the method is cell-local, a multi-GPU run would shard cells; not built)", file=sys.stderr)
@@ -160,8 +221,10 @@ def main() -> int:
     prim = torch.tensor(density_wave(np.mod(x.cpu().numpy().T, 1.0)).T.copy(), device="cuda")
     u = cd.prim_to_cons(prim)
     u0 = u.clone()
+    copy_bytes = 0
     if args.copy_probe_mib:
         n = args.copy_probe_mib * 2**20 // 8
+        copy_bytes = n * 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
@@ -193,7 +256,7 @@ def main() -> int:
     ms_per_step = 1e3 * elapsed / args.steps
     value = cd.ndof * 5 * args.steps / elapsed
     achieved = (k_bytes / k_launches) / (k_ms / k_launches * 1e-3) / 1e9 if k_launches else None
-    traffic = measured_traffic(args.workload, k_bytes / max(k_launches, 1))
+    traffic = measured_traffic(args.workload, args.precision, k_bytes / max(k_launches, 1))
     out = {
         "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -201,14 +264,15 @@ def main() -> int:
         "dtype": "f64" if args.precision == "fp64" else "f64 (predictor preconditioner f32)",
         "data": "synthetic",
         "config": {
-            "workload": wl["desc"], "cells": cd.n_cells, "ndof": cd.ndof, "subtets": cd.n_subtets,
+            "workload": wl["desc"], "name": args.workload, "cells": cd.n_cells, "ndof": cd.ndof, "subtets": cd.n_subtets,
             "N": wl["N"], "cfl": args.cfl, "dt_last": dt, "predictor_iters_mean": float(np.mean(iters)),
             "anderson_depth": args.depth, "tol": args.tol,
         },
+        "copy_probe_bytes": copy_bytes,
         "roofline": {
-            "kernel": ("k_minv<nc,0> (FP64 M_i^-1 applied to the predictor's space-time blocks)"
-                       if args.precision == "fp64" else
-                       "k_minv_f32<nc> (FP32 scaled M_i^-1 applied to the predictor's residual blocks)"),
+            "kernel": dominant_kernel(args.precision, wl["N"]) + (
+                " (FP64 M_i^-1 applied to the predictor's space-time blocks)" if args.precision == "fp64" else
+                " (FP32 scaled M_i^-1 applied to the predictor's residual blocks)"),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
             "traffic": traffic,

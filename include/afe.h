@@ -190,6 +190,87 @@ afe_status afe_profile_read(afe_cell_data *cd, double *kernel_ms, int64_t *launc
 void afe_free(afe_cell_data *cd);
 const char *afe_last_error(void);
 
+/* Device memory build_afe_cell_data(mesh, N, params) would allocate, from
+ * the mesh's per-cell vertex, face and polygon-edge counts and the closed
+ * form of the sub-grid DOF count (Sec. 4.1); host only, no device memory.
+ * Used to admit work against a device-memory budget.  Errors: AFE_E_ARG,
+ * AFE_E_BAD_MESH (a cell without faces). */
+afe_status afe_estimate_bytes(const afe_mesh *mesh, int32_t N, const afe_params *params, size_t *bytes);
+
+/* ---------------------------------------------------------------- batches
+ *
+ * A batch steps several simulations (cell-data objects, each with its own
+ * mesh, degree, parameters and state) together: one ADER step of every
+ * attached simulation per afe_batch_step.  The predictor iterations of all
+ * simulations with the same degree and precision share each kernel launch
+ * (their cells are packed into one list of (simulation, cell) entries, cells
+ * of uneven size included); the time step of each simulation comes from its
+ * own CFL number and state (eqn.timestep) and stays on the device.  Results
+ * are bit-identical to stepping each simulation alone in a batch of one,
+ * whatever else is attached and whatever launch shape is used.
+ *
+ * Ownership: the batch references, and does not own, the attached objects
+ * and states; both must stay valid until detached or the batch is freed.
+ * An object belongs to at most one batch.  Calls on one batch must come from
+ * one host thread at a time.  The batch runs its work on a stream of its own,
+ * ordered after the work already enqueued on `stream`, and `stream` is made
+ * to wait for it before afe_batch_step returns. */
+#define AFE_BATCH_SLOTS 64
+
+typedef struct afe_batch afe_batch;
+
+/* Launch shape of the predictor iteration.  Each kernel (sub-tet fluxes and
+ * assembly, M_i^{-1} application, Anderson update) runs as a persistent grid
+ * of `x` times the number of its workgroups that fit on the device at once
+ * (x = 0: one workgroup per work item, sized from the current list length).
+ * `rounds` iterations are enqueued between two reads of the number of cells
+ * still iterating; with graph = 1 (every x > 0 required) the step's phases
+ * and each group of rounds are captured once as HIP graphs and replayed.
+ * Default {1, 0, 0, 2, 0}. */
+typedef struct {
+    double sub, minv, anderson;
+    int32_t rounds; /* 1 .. 16 */
+    int32_t graph;
+} afe_launch_shape;
+
+typedef struct {
+    int32_t status;      /* afe_status of this simulation's step            */
+    int32_t iters_min, iters_max;
+    double iters_mean;   /* predictor iterations over its cells             */
+    int32_t n_troubled;  /* cells with flattener beta > 0                   */
+    int32_t status_cell; /* first failing cell, -1 if none                  */
+    double dt;           /* time step taken                                 */
+} afe_batch_report;
+
+afe_status afe_batch_create(afe_batch **out);
+void afe_batch_free(afe_batch *b);
+
+/* Attach cd with device state u (SoA [5][ndof]) and CFL number cfl > 0;
+ * *slot (may be NULL) receives its slot index in [0, AFE_BATCH_SLOTS).
+ * Errors: AFE_E_ARG (full batch, object already in a batch, bad cfl). */
+afe_status afe_batch_attach(afe_batch *b, afe_cell_data *cd, double *u, double cfl, int32_t *slot);
+afe_status afe_batch_detach(afe_batch *b, afe_cell_data *cd);
+
+/* One step of every attached simulation; reps (host, may be NULL) has
+ * n_reps entries indexed by slot.  Returns the first failing simulation's
+ * status (its state then holds the failed update), AFE_OK if none failed. */
+afe_status afe_batch_step(afe_batch *b, afe_batch_report *reps, int32_t n_reps, void *stream);
+
+afe_status afe_batch_set_shape(afe_batch *b, const afe_launch_shape *shape);
+afe_status afe_batch_get_shape(const afe_batch *b, afe_launch_shape *shape);
+
+/* Autotuner: times one step of the attached simulations for each candidate
+ * launch shape (coordinate search over the three grid multiples, the rounds
+ * between reads and graph replay) on copies of their states, keeps the
+ * fastest and returns it in *chosen (may be NULL).  The attached states are
+ * not modified.  Allocates temporary device memory for the copies. */
+afe_status afe_batch_tune(afe_batch *b, void *stream, afe_launch_shape *chosen);
+
+/* As afe_profile_enable / afe_profile_read for the batch's M_i^{-1} launches
+ * of its first group of simulations (graph replay is off while enabled). */
+afe_status afe_batch_profile_enable(afe_batch *b, int32_t enable);
+afe_status afe_batch_profile_read(afe_batch *b, double *kernel_ms, int64_t *launches, double *bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,8 +28,12 @@ EXPORTED = [
     "build_afe_cell_data", "afe_query", "afe_cell_dof_ptr", "afe_dof_coords", "afe_connectivity",
     "afe_prim_to_cons", "ader_cfl_dt", "ader_predict", "ader_correct", "ader_step",
     "afe_predictor_state", "afe_cell_diagnostics", "afe_free", "afe_last_error", "afe_subgrid_sizes",
-    "afe_subgrid_host", "afe_profile_enable", "afe_profile_read",
+    "afe_subgrid_host", "afe_profile_enable", "afe_profile_read", "afe_estimate_bytes",
+    "afe_batch_create", "afe_batch_free", "afe_batch_attach", "afe_batch_detach", "afe_batch_step",
+    "afe_batch_set_shape", "afe_batch_get_shape", "afe_batch_tune", "afe_batch_profile_enable",
+    "afe_batch_profile_read",
 ]
+BATCH_SLOTS = 64
 
 
 class AfeError(RuntimeError):
@@ -71,6 +75,21 @@ class _Report(ctypes.Structure):
     ]
 
 
+class _Shape(ctypes.Structure):
+    _fields_ = [
+        ("sub", ctypes.c_double), ("minv", ctypes.c_double), ("anderson", ctypes.c_double),
+        ("rounds", ctypes.c_int32), ("graph", ctypes.c_int32),
+    ]
+
+
+class _BatchReport(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32), ("iters_min", ctypes.c_int32), ("iters_max", ctypes.c_int32),
+        ("iters_mean", ctypes.c_double), ("n_troubled", ctypes.c_int32), ("status_cell", ctypes.c_int32),
+        ("dt", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -102,6 +121,18 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afe_last_error": ([], ctypes.c_char_p),
         "afe_profile_enable": ([vp, i32], i32),
         "afe_profile_read": ([vp, vp, vp, vp], i32),
+        "afe_estimate_bytes": ([ctypes.POINTER(_Mesh), i32, ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_size_t)],
+                               i32),
+        "afe_batch_create": ([ctypes.POINTER(vp)], i32),
+        "afe_batch_free": ([vp], None),
+        "afe_batch_attach": ([vp, vp, vp, dbl, ctypes.POINTER(i32)], i32),
+        "afe_batch_detach": ([vp, vp], i32),
+        "afe_batch_step": ([vp, ctypes.POINTER(_BatchReport), i32, vp], i32),
+        "afe_batch_set_shape": ([vp, ctypes.POINTER(_Shape)], i32),
+        "afe_batch_get_shape": ([vp, ctypes.POINTER(_Shape)], i32),
+        "afe_batch_tune": ([vp, vp, ctypes.POINTER(_Shape)], i32),
+        "afe_batch_profile_enable": ([vp, i32], i32),
+        "afe_batch_profile_read": ([vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -170,6 +201,17 @@ def _c_mesh(mesh: dict):
                arrs["face_vtx"].ctypes.data, arrs["face_vshift"].ctypes.data, arrs["face_cell"].ctypes.data,
                arrs["nbr_shift"].ctypes.data, int(mesh["n_cells"]), float(mesh["box"]))
     return cm, arrs
+
+
+def estimate_bytes(mesh: dict, N: int, params: Params | None = None) -> int:
+    """Device bytes a CellData of this mesh, degree and parameters would hold
+    (host-only closed form over the mesh's cell counts)."""
+    lib = load()
+    cm, keep = _c_mesh(mesh)
+    cp = (params or Params()).c()
+    out = ctypes.c_size_t()
+    _check(lib.afe_estimate_bytes(ctypes.byref(cm), N, ctypes.byref(cp), ctypes.byref(out)))
+    return int(out.value)
 
 
 def subgrid_host(mesh: dict, N: int) -> dict:
@@ -293,3 +335,106 @@ class CellData:
         mu = np.zeros(self.n_cells, dtype=np.float64)
         _check(_lib.afe_cell_diagnostics(self._h, it.ctypes.data, mu.ctypes.data, _stream(stream)))
         return it, mu
+
+
+@dataclass
+class LaunchShape:
+    """Predictor launch shape: persistent grid multiples (0 = one workgroup
+    per work item), iterations between reads of the list lengths, graph replay."""
+    sub: float = 1.0
+    minv: float = 0.0
+    anderson: float = 0.0
+    rounds: int = 2
+    graph: bool = False
+
+    def c(self) -> _Shape:
+        return _Shape(self.sub, self.minv, self.anderson, self.rounds, int(self.graph))
+
+    @staticmethod
+    def of(c: _Shape) -> "LaunchShape":
+        return LaunchShape(c.sub, c.minv, c.anderson, int(c.rounds), bool(c.graph))
+
+
+@dataclass
+class BatchReport:
+    status: str
+    iters_min: int
+    iters_max: int
+    iters_mean: float
+    n_troubled: int
+    status_cell: int
+    dt: float
+
+
+class Batch:
+    """Several simulations stepped together (afe_batch): one ADER step of
+    every attached CellData per step(), predictor launches shared by the
+    simulations of one degree and precision, each with its own CFL time step."""
+
+    def __init__(self):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.afe_batch_create(ctypes.byref(h)))
+        self._h = h
+        self._members = {}  # slot -> (CellData, state tensor), kept alive while attached
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _lib.afe_batch_free(self._h)
+            self._h = None
+            self._members.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def attach(self, cd: CellData, u, cfl: float) -> int:
+        slot = ctypes.c_int32()
+        _check(_lib.afe_batch_attach(self._h, cd._h, _dev(u), float(cfl), ctypes.byref(slot)))
+        self._members[int(slot.value)] = (cd, u)
+        return int(slot.value)
+
+    def detach(self, cd: CellData) -> None:
+        _check(_lib.afe_batch_detach(self._h, cd._h))
+        for k in [k for k, (c, _) in self._members.items() if c is cd]:
+            del self._members[k]
+
+    def step(self, stream=None, check: bool = True) -> dict:
+        """One step of every attached simulation; {slot: BatchReport}.  With
+        check, a failed simulation raises AfeError after the reports are filled."""
+        reps = (_BatchReport * BATCH_SLOTS)()
+        code = _lib.afe_batch_step(self._h, reps, BATCH_SLOTS, _stream(stream))
+        out = {k: BatchReport(STATUS_NAMES.get(reps[k].status, str(reps[k].status)), reps[k].iters_min,
+                              reps[k].iters_max, reps[k].iters_mean, reps[k].n_troubled, reps[k].status_cell,
+                              reps[k].dt) for k in self._members}
+        if check:
+            _check(code)
+        return out
+
+    @property
+    def shape(self) -> LaunchShape:
+        c = _Shape()
+        _check(_lib.afe_batch_get_shape(self._h, ctypes.byref(c)))
+        return LaunchShape.of(c)
+
+    @shape.setter
+    def shape(self, sh: LaunchShape) -> None:
+        c = sh.c()
+        _check(_lib.afe_batch_set_shape(self._h, ctypes.byref(c)))
+
+    def tune(self, stream=None) -> LaunchShape:
+        c = _Shape()
+        _check(_lib.afe_batch_tune(self._h, _stream(stream), ctypes.byref(c)))
+        return LaunchShape.of(c)
+
+    def profile_enable(self, on: bool = True) -> None:
+        _check(_lib.afe_batch_profile_enable(self._h, int(on)))
+
+    def profile_read(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        b = ctypes.c_double()
+        _check(_lib.afe_batch_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return float(ms.value), int(n.value), float(b.value)

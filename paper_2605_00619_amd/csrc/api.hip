@@ -1,11 +1,13 @@
 // C ABI of libafe (see include/afe.h): object life cycle, buffers, and the
-// host-side sequencing of the step kernels.
+// host-side sequencing of the step kernels for one simulation or a batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -30,6 +32,86 @@ afe_status fail(afe_status s, const std::string &msg) {
         if (e_ != hipSuccess) return fail(AFE_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+#define AFE_TRY(expr)                \
+    do {                             \
+        afe_status s_ = (expr);      \
+        if (s_ != AFE_OK) return s_; \
+    } while (0)
+
+constexpr int kStatusWords = 8;
+
+// One group of slots with the same degree and precision: they share the
+// predictor's launches through one list of (slot, cell) entries.
+struct Group {
+    int N = 0, mixed = 0;
+    std::vector<int> slots;
+    std::vector<int64_t> base;  // list offset of each slot's cells
+    int64_t cells = 0;
+    int max_cell_dofs = 0, max_cell_subtets = 0;
+    int32_t *lists = nullptr;   // device [2][cells] (ping-pong)
+    int32_t *counts = nullptr;  // device [2]
+    afe::IterShape resident;    // workgroups that fit at once, per kernel
+    afe::IterShape shape;       // grids in use
+};
+
+// Sequencing of the step kernels over a set of slots.  A cell-data object
+// owns an engine with itself as its only slot; a batch owns one with many.
+struct Engine {
+    afe::DevSlot *d_tab = nullptr;     // device table [kMaxSlots]
+    std::vector<afe::DevSlot> tab;     // host image of the table
+    std::vector<afe_cell_data *> cds;  // slot -> object (nullptr: free)
+    std::vector<double *> u;           // slot -> state
+    std::vector<double> cfl;           // slot -> CFL number (batch steps)
+    std::vector<Group> groups;
+    bool dirty = true;                 // table or grouping changed since the last upload
+    afe_launch_shape shape{1.0, 0.0, 0.0, 2, 0};  // the tuner's usual choice
+    int32_t *h_counts = nullptr;       // pinned [kMaxSlots]
+    hipStream_t own = nullptr;         // private stream (graph capture needs a non-null stream)
+    hipEvent_t join[2] = {nullptr, nullptr};
+    hipGraphExec_t g_pre = nullptr, g_post = nullptr, g_chunk[2] = {nullptr, nullptr};
+    // profiling of the first group's M^{-1} launches
+    bool prof_on = false;
+    afe::ProfileHooks hooks{};
+    unsigned long long *d_bytes = nullptr;
+    double prof_ms = 0.0;
+    int64_t prof_launches = 0;
+
+    Engine() : tab(afe::kMaxSlots), cds(afe::kMaxSlots, nullptr), u(afe::kMaxSlots, nullptr), cfl(afe::kMaxSlots, 0.0) {}
+    ~Engine() {
+        drop_graphs();
+        drop_groups();
+        for (int i = 0; i < afe::kMaxRounds; ++i) {
+            if (hooks.start[i]) (void)hipEventDestroy(hooks.start[i]);
+            if (hooks.stop[i]) (void)hipEventDestroy(hooks.stop[i]);
+        }
+        if (d_bytes) (void)hipFree(d_bytes);
+        if (d_tab) (void)hipFree(d_tab);
+        if (h_counts) (void)hipHostFree(h_counts);
+        for (auto &e : join)
+            if (e) (void)hipEventDestroy(e);
+        if (own) (void)hipStreamDestroy(own);
+    }
+    void drop_graphs() {
+        for (hipGraphExec_t *g : {&g_pre, &g_post, &g_chunk[0], &g_chunk[1]})
+            if (*g) {
+                (void)hipGraphExecDestroy(*g);
+                *g = nullptr;
+            }
+    }
+    void drop_groups() {
+        for (auto &gr : groups) {
+            if (gr.lists) (void)hipFree(gr.lists);
+            if (gr.counts) (void)hipFree(gr.counts);
+        }
+        groups.clear();
+    }
+    int n_slots() const {
+        int n = 0;
+        for (auto *c : cds) n += c != nullptr;
+        return n;
+    }
+};
+
 }  // namespace
 
 struct afe_cell_data {
@@ -39,15 +121,11 @@ struct afe_cell_data {
     afe_params params{};
     std::vector<void *> allocs;
     size_t bytes = 0;
-    double *d_scalar = nullptr;  // device scratch scalar (CFL max)
-    int32_t *h_status = nullptr; // pinned host copy of the status word
-    double *h_scalar = nullptr;
-    // profiling of the predictor's M^{-1} kernel
-    bool prof_on = false;
-    afe::ProfileHooks hooks{};
-    unsigned long long *h_bytes = nullptr;
-    double prof_ms = 0.0;
-    int64_t prof_launches = 0;
+    double *d_scalar = nullptr;  // device scratch scalar (largest CFL term)
+    int32_t *h_status = nullptr; // pinned host copy of the status words
+    double *h_scalar = nullptr;  // pinned host scalars [2]: largest CFL term, dt
+    Engine solo;                 // this object as the only slot
+    afe_batch *batch = nullptr;  // batch it is attached to, if any
 
     template <typename T>
     hipError_t alloc(T *&p, size_t count) {
@@ -71,35 +149,350 @@ struct afe_cell_data {
         return e;
     }
     ~afe_cell_data() {
-        for (int i = 0; i < afe::kSyncEvery; ++i) {
-            if (hooks.start[i]) (void)hipEventDestroy(hooks.start[i]);
-            if (hooks.stop[i]) (void)hipEventDestroy(hooks.stop[i]);
-        }
-        if (h_bytes) (void)hipHostFree(h_bytes);
         for (void *p : allocs) (void)hipFree(p);
         if (h_status) (void)hipHostFree(h_status);
         if (h_scalar) (void)hipHostFree(h_scalar);
     }
 };
 
+struct afe_batch {
+    Engine eng;
+};
+
 namespace {
 
-size_t estimate_bytes(const afe::HostGrid &h, int depth, bool mixed) {
-    const size_t nc = size_t(5) * (h.N + 1);
-    size_t b = 0;
-    for (int c = 0; c < h.n_cells; ++c) {
-        size_t n = size_t(h.dof_ptr[c + 1] - h.dof_ptr[c]);
-        b += n * ((n + 15) & ~size_t(15)) * sizeof(double);
-        if (mixed) b += n * ((n + 31) & ~size_t(31)) * sizeof(float);
+// Device bytes of one simulation (the allocations of build_afe_cell_data).
+size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub, int max_cell_dofs, int depth,
+                      bool mixed) {
+    const size_t nc = size_t(5) * (N + 1);
+    const size_t np = size_t(N + 1) * (N + 2) * (N + 3) / 6, nf = size_t(N + 1) * (N + 2) / 2;
+    const size_t n_cells = cell_dofs.size();
+    size_t b = 0, ndof = 0;
+    for (int64_t n : cell_dofs) {
+        b += size_t(n) * size_t((n + 15) & ~int64_t(15)) * sizeof(double);
+        if (mixed) b += size_t(n) * size_t((n + 31) & ~int64_t(31)) * sizeof(float);
+        ndof += size_t(n);
     }
-    b += size_t(h.ndof) * nc * sizeof(double) * (5 + 2 * size_t(std::max(depth, 1)));
-    b += size_t(h.n_cells) * ((h.max_cell_dofs + 63) / 64) * 130 * sizeof(double);
-    b += size_t(h.nsub) * h.np * nc * sizeof(double);
-    b += size_t(h.nsub) * h.nf * 25 * sizeof(double) + size_t(h.nsub) * h.np * 5 * sizeof(double);
-    b += size_t(h.ndof) * (5 * 8 + 3 * 8 + 8 + 4 + 8);
-    b += size_t(h.nsub) * (h.np * 4 + 10 * 8 + 4 * 8 + 4 + 4 + h.nf * 4);
-    b += size_t(h.n_cells) * ((2 * 63 * 63 + 63) * 8 + 64);
+    b += ndof * nc * sizeof(double) * (5 + 2 * size_t(std::max(depth, 1)));
+    if (mixed) b += ndof * nc * sizeof(float);
+    b += n_cells * size_t((max_cell_dofs + 63) / 64) * 130 * sizeof(double);
+    b += size_t(nsub) * np * nc * sizeof(double);
+    b += size_t(nsub) * nf * 25 * sizeof(double) + size_t(nsub) * np * 5 * sizeof(double);  // traces, faces, volume
+    b += ndof * (5 * 8 + 8 + 4 + 8 + 4 + 4);  // rhs, column sums, DOF cell, scales, incidence offsets
+    b += size_t(nsub) * (2 * np * 4 + 10 * 8 + 4 * 8 + 4 + 4 + 2 * nf * 4);  // connectivity, geometry, incidences
+    b += n_cells * ((2 * 63 * 63 + 2 * 63) * 8 + 88);  // Gram / Cholesky, coefficients, per-cell scalars and offsets
+    b += 2 * n_cells * sizeof(int32_t);           // predictor list of a batch of one
     return b;
+}
+
+afe_status check_params(const afe_params *p) {
+    if (p->precision != AFE_FP64 && p->precision != AFE_MIXED) return fail(AFE_E_ARG, "unknown precision");
+    if (p->accel_depth < 0 || p->accel_depth > 63) return fail(AFE_E_ARG, "accel_depth must be in [0, 63]");
+    if (p->max_iter < 1) return fail(AFE_E_ARG, "max_iter must be >= 1");
+    if (!(p->gamma > 1.0) || p->mu < 0.0 || !(p->tol >= 0.0))
+        return fail(AFE_E_ARG, "invalid physics or tolerance parameter");
+    return AFE_OK;
+}
+
+// ----------------------------------------------------------------- engine
+
+afe_status ensure_stream(Engine &E) {
+    if (!E.own) {
+        HIP_TRY(hipStreamCreateWithFlags(&E.own, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&E.join[0], hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&E.join[1], hipEventDisableTiming));
+    }
+    return AFE_OK;
+}
+
+// Regroup the slots and upload the table when attachments changed.
+afe_status sync_layout(Engine &E, hipStream_t s) {
+    if (!E.d_tab) {
+        HIP_TRY(hipMalloc(&E.d_tab, sizeof(afe::DevSlot) * afe::kMaxSlots));
+        HIP_TRY(hipHostMalloc(&E.h_counts, sizeof(int32_t) * afe::kMaxSlots, hipHostMallocDefault));
+    }
+    if (!E.dirty) return AFE_OK;
+    HIP_TRY(hipStreamSynchronize(s));
+    E.drop_graphs();
+    E.drop_groups();
+    std::map<std::pair<int, int>, int> gid;
+    for (int sl = 0; sl < afe::kMaxSlots; ++sl) {
+        afe_cell_data *cd = E.cds[sl];
+        if (!cd) continue;
+        E.tab[sl].g = cd->g;
+        E.tab[sl].w = cd->w;
+        E.tab[sl].w.u = E.u[sl];
+        const auto key = std::make_pair(cd->g.N, cd->g.mixed);
+        auto it = gid.find(key);
+        if (it == gid.end()) {
+            it = gid.emplace(key, int(E.groups.size())).first;
+            Group gr;
+            gr.N = key.first;
+            gr.mixed = key.second;
+            gr.resident = afe::resident_shape(gr.N, gr.mixed);
+            E.groups.push_back(gr);
+        }
+        Group &gr = E.groups[it->second];
+        gr.slots.push_back(sl);
+        gr.base.push_back(gr.cells);
+        gr.cells += cd->host.n_cells;
+        gr.max_cell_dofs = std::max(gr.max_cell_dofs, cd->host.max_cell_dofs);
+        gr.max_cell_subtets = std::max(gr.max_cell_subtets, cd->host.max_cell_subtets);
+    }
+    for (auto &gr : E.groups) {
+        if (gr.cells > INT_MAX / 64) return fail(AFE_E_ARG, "too many cells in one group");
+        HIP_TRY(hipMalloc(&gr.lists, sizeof(int32_t) * 2 * size_t(gr.cells)));
+        HIP_TRY(hipMalloc(&gr.counts, sizeof(int32_t) * 2));
+    }
+    HIP_TRY(hipMemcpy(E.d_tab, E.tab.data(), sizeof(afe::DevSlot) * afe::kMaxSlots, hipMemcpyHostToDevice));
+    E.dirty = false;
+    return AFE_OK;
+}
+
+void apply_shape(Engine &E) {
+    auto scale = [](double x, int res) { return x > 0.0 ? std::max(1, int(std::lround(x * res))) : 0; };
+    for (auto &gr : E.groups) {
+        gr.shape.g_sub = scale(E.shape.sub, gr.resident.g_sub);
+        gr.shape.g_gather = scale(E.shape.sub, gr.resident.g_gather);
+        gr.shape.g_minv = scale(E.shape.minv, gr.resident.g_minv);
+        gr.shape.g_dots = scale(E.shape.anderson, gr.resident.g_dots);
+        gr.shape.g_solve = scale(E.shape.anderson, gr.resident.g_solve);
+        gr.shape.g_update = scale(E.shape.anderson, gr.resident.g_update);
+    }
+}
+
+bool persistent(const Engine &E) { return E.shape.sub > 0.0 && E.shape.minv > 0.0 && E.shape.anderson > 0.0; }
+
+// Start of a step for every slot: status cleared, detector (Sec. 4.5), the
+// time step (batch: from the CFL number, on the device) and the predictor's
+// initial iterate and lists.
+afe_status launch_pre(Engine &E, bool cfl_dt, hipStream_t s) {
+    for (auto &gr : E.groups) {
+        for (size_t i = 0; i < gr.slots.size(); ++i) {
+            const int sl = gr.slots[i];
+            afe_cell_data *cd = E.cds[sl];
+            const afe::DevWork &w = E.tab[sl].w;
+            HIP_TRY(afe::launch_reset_status(cd->g, w, s));
+            HIP_TRY(afe::launch_detect(cd->g, w, E.u[sl], s));
+            if (cfl_dt) HIP_TRY(afe::launch_cfl_dt(cd->g, w, E.cfl[sl], cd->host.h_min, cd->d_scalar, s));
+            HIP_TRY(afe::launch_pred_init(cd->g, w, sl, gr.lists, gr.base[i], s));
+        }
+        HIP_TRY(afe::launch_set_count(gr.counts, int(gr.cells), s));
+    }
+    return AFE_OK;
+}
+
+// One predictor iteration of every group, iteration index it (list parity).
+afe_status launch_round(Engine &E, int it, const std::vector<int> &upper, int prof_slot, hipStream_t s) {
+    for (size_t gi = 0; gi < E.groups.size(); ++gi) {
+        Group &gr = E.groups[gi];
+        const int cur = it % 2, nxt = 1 - cur;
+        afe::RoundArgs a{};
+        a.N = gr.N;
+        a.mixed = gr.mixed;
+        a.tab = E.d_tab;
+        a.list = gr.lists + size_t(cur) * gr.cells;
+        a.count = gr.counts + cur;
+        a.next = gr.lists + size_t(nxt) * gr.cells;
+        a.next_count = gr.counts + nxt;
+        a.n_upper = upper.empty() ? int(gr.cells) : upper[gi];
+        a.max_cell_dofs = gr.max_cell_dofs;
+        a.max_cell_subtets = gr.max_cell_subtets;
+        a.shape = gr.shape;
+        const bool prof = gi == 0 && prof_slot >= 0;
+        a.ev0 = prof ? E.hooks.start[prof_slot] : nullptr;
+        a.ev1 = prof ? E.hooks.stop[prof_slot] : nullptr;
+        a.bytes = prof ? E.d_bytes : nullptr;
+        HIP_TRY(afe::launch_pred_round(a, s));
+    }
+    return AFE_OK;
+}
+
+afe_status capture(Engine &E, hipGraphExec_t *out, hipStream_t s, afe_status (*body)(Engine &, int, hipStream_t),
+                   int arg) {
+    hipGraph_t graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    afe_status st = body(E, arg, s);
+    hipError_t e = hipStreamEndCapture(s, &graph);
+    if (st != AFE_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(AFE_E_HIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(AFE_E_HIP, std::string("graph instantiation: ") + hipGetErrorString(e));
+    return AFE_OK;
+}
+
+afe_status chunk_body(Engine &E, int parity, hipStream_t s) {
+    static const std::vector<int> none;
+    for (int r = 0; r < E.shape.rounds; ++r) AFE_TRY(launch_round(E, parity + r, none, -1, s));
+    return AFE_OK;
+}
+
+// Predictor iterations until every list is empty: `rounds` iterations are
+// enqueued between two reads of the list lengths (with grids sized from the
+// lengths: one per read while lists are long).  Cells leave the lists when
+// converged or at their max_iter.
+afe_status iterate(Engine &E, hipStream_t s) {
+    int max_it = 0;
+    for (auto &gr : E.groups)
+        for (int sl : gr.slots) max_it = std::max(max_it, E.cds[sl]->params.max_iter);
+    const bool pers = persistent(E);
+    const bool graph = E.shape.graph && pers && !E.prof_on;
+    std::vector<int> upper(E.groups.size());
+    int64_t total = 0;
+    for (size_t gi = 0; gi < E.groups.size(); ++gi) total += upper[gi] = int(E.groups[gi].cells);
+    int it = 0;
+    while (total > 0 && it < max_it) {
+        int R = E.shape.rounds;
+        if (graph) {
+            const int p = it % 2;
+            if (!E.g_chunk[p]) AFE_TRY(capture(E, &E.g_chunk[p], s, chunk_body, p));
+            HIP_TRY(hipGraphLaunch(E.g_chunk[p], s));
+        } else {
+            int64_t longest = 0;
+            for (int v : upper) longest = std::max<int64_t>(longest, v);
+            if (!pers && longest > 256) R = 1;  // long lists shrink fast: resize the grids every iteration
+            for (int r = 0; r < R; ++r)
+                AFE_TRY(launch_round(E, it + r, upper, E.prof_on && r < afe::kMaxRounds ? r : -1, s));
+        }
+        it += R;
+        for (size_t gi = 0; gi < E.groups.size(); ++gi)
+            HIP_TRY(hipMemcpyAsync(E.h_counts + gi, E.groups[gi].counts + (it % 2), sizeof(int32_t),
+                                   hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        total = 0;
+        for (size_t gi = 0; gi < E.groups.size(); ++gi) total += upper[gi] = E.h_counts[gi];
+        if (E.prof_on && !graph) {
+            for (int r = 0; r < std::min(R, afe::kMaxRounds); ++r) {
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, E.hooks.start[r], E.hooks.stop[r]));
+                E.prof_ms += ms;
+                E.prof_launches += 1;
+            }
+        }
+    }
+    return AFE_OK;
+}
+
+// End of a step for every slot: time integrals of the predictor, corrector
+// (Sec. 4.4) with the positivity check, iteration statistics.
+afe_status launch_post(Engine &E, hipStream_t s) {
+    for (auto &gr : E.groups)
+        for (int sl : gr.slots) {
+            afe_cell_data *cd = E.cds[sl];
+            const afe::DevWork &w = E.tab[sl].w;
+            HIP_TRY(afe::launch_pred_post(cd->g, w, s));
+            HIP_TRY(afe::launch_correct(cd->g, w, E.u[sl], s));
+            HIP_TRY(afe::launch_step_stats(cd->g, w, s));
+        }
+    return AFE_OK;
+}
+
+afe_status pre_body(Engine &E, int, hipStream_t s) { return launch_pre(E, true, s); }
+afe_status post_body(Engine &E, int, hipStream_t s) { return launch_post(E, s); }
+
+afe_status profile_enable(Engine &E, int32_t enable) {
+    if (enable && !E.d_bytes) {
+        for (int i = 0; i < afe::kMaxRounds; ++i) {
+            HIP_TRY(hipEventCreate(&E.hooks.start[i]));
+            HIP_TRY(hipEventCreate(&E.hooks.stop[i]));
+        }
+        HIP_TRY(hipMalloc(&E.d_bytes, sizeof(unsigned long long)));
+    }
+    E.prof_on = enable != 0;
+    E.prof_ms = 0.0;
+    E.prof_launches = 0;
+    if (E.d_bytes) HIP_TRY(hipMemset(E.d_bytes, 0, sizeof(unsigned long long)));
+    return AFE_OK;
+}
+
+afe_status profile_read(Engine &E, double *kernel_ms, int64_t *launches, double *bytes) {
+    unsigned long long b = 0;
+    if (E.d_bytes) HIP_TRY(hipMemcpy(&b, E.d_bytes, sizeof(b), hipMemcpyDeviceToHost));
+    if (kernel_ms) *kernel_ms = E.prof_ms;
+    if (launches) *launches = E.prof_launches;
+    if (bytes) *bytes = double(b);
+    return AFE_OK;
+}
+
+afe_status status_of(int flags) {
+    if (flags & afe::kStatusNonfinite) return AFE_E_NONFINITE;
+    if (flags & afe::kStatusNoConv) return AFE_E_NO_CONVERGENCE;
+    if (flags & afe::kStatusPositivity) return AFE_E_POSITIVITY;
+    return AFE_OK;
+}
+
+const char *status_text(afe_status st) {
+    switch (st) {
+        case AFE_E_NONFINITE: return "non-finite state after the update";
+        case AFE_E_NO_CONVERGENCE: return "predictor did not converge";
+        case AFE_E_POSITIVITY: return "density or pressure not positive";
+        default: return "";
+    }
+}
+
+// One step of every slot of a batch on stream s (the engine's own stream).
+afe_status batch_step_on(Engine &E, afe_batch_report *reps, int32_t n_reps, hipStream_t s) {
+    apply_shape(E);
+    const bool graph = E.shape.graph && persistent(E) && !E.prof_on;
+    if (graph) {
+        if (!E.g_pre) AFE_TRY(capture(E, &E.g_pre, s, pre_body, 0));
+        HIP_TRY(hipGraphLaunch(E.g_pre, s));
+    } else {
+        AFE_TRY(launch_pre(E, true, s));
+    }
+    AFE_TRY(iterate(E, s));
+    if (graph) {
+        if (!E.g_post) AFE_TRY(capture(E, &E.g_post, s, post_body, 0));
+        HIP_TRY(hipGraphLaunch(E.g_post, s));
+    } else {
+        AFE_TRY(launch_post(E, s));
+    }
+    for (int sl = 0; sl < afe::kMaxSlots; ++sl) {
+        afe_cell_data *cd = E.cds[sl];
+        if (!cd) continue;
+        HIP_TRY(hipMemcpyAsync(cd->h_status, cd->w.status, kStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(cd->h_scalar + 1, cd->w.dt, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    afe_status first = AFE_OK;
+    for (int sl = 0; sl < afe::kMaxSlots; ++sl) {
+        afe_cell_data *cd = E.cds[sl];
+        if (!cd) continue;
+        const int32_t *h = cd->h_status;
+        const afe_status st = status_of(h[0]);
+        if (first == AFE_OK && st != AFE_OK) first = st;
+        if (reps && sl < n_reps) {
+            afe_batch_report &r = reps[sl];
+            r.status = st;
+            r.iters_min = h[4];
+            r.iters_max = h[5];
+            unsigned long long sum = 0;
+            std::memcpy(&sum, h + 6, sizeof(sum));
+            r.iters_mean = cd->host.n_cells ? double(sum) / double(cd->host.n_cells) : 0.0;
+            r.n_troubled = h[3];
+            r.status_cell = h[0] ? h[1] : -1;
+            r.dt = cd->h_scalar[1];
+        }
+    }
+    if (first != AFE_OK) return fail(first, status_text(first));
+    return AFE_OK;
+}
+
+// Run `fn` on the engine's stream, ordered after the work on `user`, and
+// order the later work on `user` after it.
+template <typename F>
+afe_status on_own_stream(Engine &E, hipStream_t user, F &&fn) {
+    AFE_TRY(ensure_stream(E));
+    HIP_TRY(hipEventRecord(E.join[0], user));
+    HIP_TRY(hipStreamWaitEvent(E.own, E.join[0], 0));
+    afe_status st = fn(E.own);
+    HIP_TRY(hipEventRecord(E.join[1], E.own));
+    HIP_TRY(hipStreamWaitEvent(user, E.join[1], 0));
+    return st;
 }
 
 }  // namespace
@@ -108,17 +501,16 @@ extern "C" {
 
 const char *afe_last_error(void) { return g_err.c_str(); }
 
-void afe_free(afe_cell_data *cd) { delete cd; }
+void afe_free(afe_cell_data *cd) {
+    if (cd && cd->batch) (void)afe_batch_detach(cd->batch, cd);
+    delete cd;
+}
 
 afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params *params, void *stream,
                                afe_cell_data **out) {
     if (!mesh || !params || !out) return fail(AFE_E_ARG, "null argument");
     *out = nullptr;
-    if (params->precision != AFE_FP64 && params->precision != AFE_MIXED) return fail(AFE_E_ARG, "unknown precision");
-    if (params->accel_depth < 0 || params->accel_depth > 63) return fail(AFE_E_ARG, "accel_depth must be in [0, 63]");
-    if (params->max_iter < 1) return fail(AFE_E_ARG, "max_iter must be >= 1");
-    if (!(params->gamma > 1.0) || params->mu < 0.0 || !(params->tol >= 0.0))
-        return fail(AFE_E_ARG, "invalid physics or tolerance parameter");
+    AFE_TRY(check_params(params));
     hipStream_t s = static_cast<hipStream_t>(stream);
     afe_cell_data *cd = new (std::nothrow) afe_cell_data();
     if (!cd) return fail(AFE_E_ARG, "out of host memory");
@@ -131,7 +523,13 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     cd->params = *params;
     const afe::HostGrid &h = cd->host;
     const int depth = params->accel_depth;
-    size_t need = estimate_bytes(h, depth, params->precision == AFE_MIXED);
+    if (h.n_cells >= afe::kMaxCellsPerSlot) {
+        delete cd;
+        return fail(AFE_E_ARG, "too many cells");
+    }
+    std::vector<int64_t> cell_dofs(h.n_cells);
+    for (int c = 0; c < h.n_cells; ++c) cell_dofs[c] = h.dof_ptr[c + 1] - h.dof_ptr[c];
+    size_t need = estimate_bytes(N, cell_dofs, h.nsub, h.max_cell_dofs, depth, params->precision == AFE_MIXED);
     if (params->hbm_budget > 0 && need > params->hbm_budget) {
         delete cd;
         return fail(AFE_E_HBM_BUDGET, "needs " + std::to_string(need) + " bytes, budget " +
@@ -214,16 +612,16 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     const size_t nd = size_t(h.ndof);
     const int dslots = std::max(depth, 1);
     w.depth = depth;
+    w.tol = params->tol;
+    w.max_iter = params->max_iter;
     if ((e = cd->alloc(g.minv, size_t(minv_ptr[h.n_cells]))) != hipSuccess ||
         (e = cd->alloc(g.dscale, nd)) != hipSuccess ||
         (e = cd->alloc(g.minv32, size_t(minv32_ptr[h.n_cells]))) != hipSuccess ||
         (e = cd->alloc(w.R32, g.mixed ? nd * nc : 1)) != hipSuccess ||
         (e = cd->alloc(w.x, nd * nc)) != hipSuccess || (e = cd->alloc(w.R, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.S, nd * nc)) != hipSuccess || (e = cd->alloc(w.fprev, nd * nc)) != hipSuccess ||
-        (e = cd->alloc(w.gprev, nd * nc)) != hipSuccess || 
+        (e = cd->alloc(w.gprev, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.part, size_t(h.n_cells) * ((h.max_cell_dofs + 63) / 64) * 130)) != hipSuccess ||
-        (e = cd->alloc(w.gamma, size_t(h.n_cells) * 63)) != hipSuccess ||
-        (e = cd->alloc(w.kuse, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.dF, nd * nc * dslots)) != hipSuccess ||
         (e = cd->alloc(w.dG, nd * nc * dslots)) != hipSuccess ||
         (e = cd->alloc(w.gram, size_t(h.n_cells) * (2 * 63 * 63 + 63))) != hipSuccess ||
@@ -236,12 +634,13 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(w.mu_cell, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.beta, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.cflterm, size_t(h.n_cells))) != hipSuccess ||
-        (e = cd->alloc(w.alist, size_t(h.n_cells) * 2)) != hipSuccess ||
-        (e = cd->alloc(w.acount, 2)) != hipSuccess ||
         (e = cd->alloc(w.iters, size_t(h.n_cells))) != hipSuccess ||
-        (e = cd->alloc(w.status, 4)) != hipSuccess || (e = cd->alloc(cd->d_scalar, 1)) != hipSuccess ||
-        (e = hipHostMalloc(&cd->h_status, 4 * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc(&cd->h_scalar, sizeof(double), hipHostMallocDefault)) != hipSuccess) {
+        (e = cd->alloc(w.gamma, size_t(h.n_cells) * 63)) != hipSuccess ||
+        (e = cd->alloc(w.kuse, size_t(h.n_cells))) != hipSuccess ||
+        (e = cd->alloc(w.dt, 1)) != hipSuccess ||
+        (e = cd->alloc(w.status, kStatusWords)) != hipSuccess || (e = cd->alloc(cd->d_scalar, 1)) != hipSuccess ||
+        (e = hipHostMalloc(&cd->h_status, kStatusWords * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc(&cd->h_scalar, 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess) {
         std::string m = hipGetErrorString(e);
         delete cd;
         return fail(e == hipErrorOutOfMemory ? AFE_E_HBM_BUDGET : AFE_E_HIP, "allocation: " + m);
@@ -254,7 +653,46 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         delete cd;
         return fail(AFE_E_HIP, "mass matrices: " + m);
     }
+    cd->solo.cds[0] = cd;
     *out = cd;
+    return AFE_OK;
+}
+
+afe_status afe_estimate_bytes(const afe_mesh *mesh, int32_t N, const afe_params *params, size_t *bytes) {
+    if (!mesh || !params || !bytes) return fail(AFE_E_ARG, "null argument");
+    if (N < 1 || N > 3) return fail(AFE_E_ARG, "N must be 1, 2 or 3");
+    if (mesh->n_cells < 1 || mesh->n_faces < 1 || !mesh->face_ptr || !mesh->face_vtx || !mesh->face_cell)
+        return fail(AFE_E_ARG, "empty mesh");
+    // per cell: V vertices, F faces, E polygon edges; its sub-grid has
+    // V + F + 1 vertices, 3E + V + F edges, 5E triangles and 2E sub-tets
+    const int nc = mesh->n_cells;
+    std::vector<int64_t> F(nc, 0), E(nc, 0);
+    std::vector<std::vector<int32_t>> verts(nc);
+    for (int f = 0; f < mesh->n_faces; ++f) {
+        const int k = mesh->face_ptr[f + 1] - mesh->face_ptr[f];
+        for (int side = 0; side < 2; ++side) {
+            const int c = mesh->face_cell[2 * f + side];
+            if (c < 0 || c >= nc) return fail(AFE_E_BAD_MESH, "face cell out of range");
+            F[c] += 1;
+            E[c] += k;
+            for (int i = mesh->face_ptr[f]; i < mesh->face_ptr[f + 1]; ++i) verts[c].push_back(mesh->face_vtx[i]);
+        }
+    }
+    const int64_t a = N - 1;
+    std::vector<int64_t> dofs(nc);
+    int64_t nsub = 0;
+    int max_dofs = 0;
+    for (int c = 0; c < nc; ++c) {
+        if (F[c] == 0) return fail(AFE_E_BAD_MESH, "cell without faces");
+        std::sort(verts[c].begin(), verts[c].end());
+        const int64_t V = std::unique(verts[c].begin(), verts[c].end()) - verts[c].begin();
+        const int64_t Ec = E[c] / 2;
+        dofs[c] = (V + F[c] + 1) + a * (3 * Ec + V + F[c]) + (a * (a - 1) / 2) * 5 * Ec +
+                  (a * (a - 1) * (a - 2) / 6) * 2 * Ec;
+        nsub += 2 * Ec;
+        max_dofs = std::max<int>(max_dofs, int(dofs[c]));
+    }
+    *bytes = estimate_bytes(N, dofs, nsub, max_dofs, params->accel_depth, params->precision == AFE_MIXED);
     return AFE_OK;
 }
 
@@ -335,7 +773,7 @@ afe_status ader_cfl_dt(afe_cell_data *cd, const double *u, double cfl, double *d
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(afe::launch_reset_status(cd->g, cd->w, s));
     HIP_TRY(afe::launch_detect(cd->g, cd->w, u, s));
-    HIP_TRY(afe::launch_cfl_max(cd->g, cd->w, cd->d_scalar, s));
+    HIP_TRY(afe::launch_cfl_dt(cd->g, cd->w, 0.0, cd->host.h_min, cd->d_scalar, s));
     HIP_TRY(hipMemcpyAsync(cd->h_scalar, cd->d_scalar, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const double smax = *cd->h_scalar;
@@ -347,105 +785,58 @@ afe_status ader_cfl_dt(afe_cell_data *cd, const double *u, double cfl, double *d
 afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *stream) {
     if (!cd || !u || !(dt > 0.0)) return fail(AFE_E_ARG, "invalid argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const auto &p = cd->params;
-    HIP_TRY(afe::launch_reset_status(cd->g, cd->w, s));
-    HIP_TRY(afe::launch_detect(cd->g, cd->w, u, s));
-    HIP_TRY(afe::launch_pred_init(cd->g, cd->w, u, s));
-    // Iterations are launched in batches of kSyncEvery without waiting: the
-    // kernels read the current list length on the device and idle blocks exit,
-    // the host only needs an upper bound, refreshed at each synchronisation.
-    int n_upper = cd->host.n_cells;
-    for (int it = 0; it < p.max_iter && n_upper > 0;) {
-        // large lists shrink fast: synchronise every iteration until few cells remain
-        const int batch_len = n_upper > 256 ? 1 : afe::kSyncEvery;
-        int batch = 0;
-        for (; batch < batch_len && it < p.max_iter; ++batch, ++it) {
-            const int cur = it % 2, nxt = 1 - cur;
-            int32_t *list = cd->w.alist + size_t(cur) * cd->host.n_cells;
-            int32_t *next = cd->w.alist + size_t(nxt) * cd->host.n_cells;
-            HIP_TRY(afe::launch_pred_iteration(cd->g, cd->w, u, dt, it, p.max_iter, p.tol, list, cd->w.acount + cur,
-                                               n_upper, next, cd->w.acount + nxt, s,
-                                               cd->prof_on ? cd->hooks.start[batch] : nullptr,
-                                               cd->prof_on ? cd->hooks.stop[batch] : nullptr,
-                                               cd->prof_on ? cd->hooks.bytes : nullptr));
-        }
-        HIP_TRY(hipMemcpyAsync(cd->h_status + 2, cd->w.acount + (it % 2), sizeof(int32_t), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        n_upper = cd->h_status[2];
-        if (cd->prof_on) {
-            for (int b = 0; b < batch; ++b) {
-                float ms = 0.0f;
-                HIP_TRY(hipEventElapsedTime(&ms, cd->hooks.start[b], cd->hooks.stop[b]));
-                cd->prof_ms += ms;
-                cd->prof_launches += 1;
-            }
-        }
+    Engine &E = cd->solo;
+    if (E.u[0] != u) {
+        E.u[0] = const_cast<double *>(u);
+        E.dirty = true;
     }
-    HIP_TRY(afe::launch_pred_post(cd->g, cd->w, dt, s));
+    AFE_TRY(sync_layout(E, s));
+    apply_shape(E);
+    HIP_TRY(afe::launch_set_dt(cd->w, dt, s));
+    AFE_TRY(launch_pre(E, false, s));
+    AFE_TRY(iterate(E, s));
+    HIP_TRY(afe::launch_pred_post(cd->g, E.tab[0].w, s));
     return AFE_OK;
 }
 
 afe_status ader_correct(afe_cell_data *cd, double *u, double dt, void *stream) {
     if (!cd || !u || !(dt > 0.0)) return fail(AFE_E_ARG, "invalid argument");
-    HIP_TRY(afe::launch_correct(cd->g, cd->w, u, dt, static_cast<hipStream_t>(stream)));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(afe::launch_set_dt(cd->w, dt, s));
+    HIP_TRY(afe::launch_correct(cd->g, cd->w, u, s));
+    HIP_TRY(afe::launch_step_stats(cd->g, cd->w, s));
     return AFE_OK;
 }
 
 afe_status ader_step(afe_cell_data *cd, double *u, double dt, afe_step_report *rep, void *stream) {
-    afe_status st = ader_predict(cd, u, dt, stream);
-    if (st != AFE_OK) return st;
-    st = ader_correct(cd, u, dt, stream);
-    if (st != AFE_OK) return st;
+    AFE_TRY(ader_predict(cd, u, dt, stream));
+    AFE_TRY(ader_correct(cd, u, dt, stream));
     hipStream_t s = static_cast<hipStream_t>(stream);
-    HIP_TRY(hipMemcpyAsync(cd->h_status, cd->w.status, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(cd->h_status, cd->w.status, kStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const int flags = cd->h_status[0];
+    const int32_t *h = cd->h_status;
     if (rep) {
-        std::vector<int32_t> it(cd->host.n_cells);
-        HIP_TRY(hipMemcpy(it.data(), cd->w.iters, it.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
-        int mn = INT_MAX, mx = 0;
-        double sum = 0.0;
-        for (int v : it) {
-            mn = std::min(mn, v);
-            mx = std::max(mx, v);
-            sum += v;
-        }
-        rep->iters_min = it.empty() ? 0 : mn;
-        rep->iters_max = mx;
-        rep->iters_mean = it.empty() ? 0.0 : sum / double(it.size());
-        rep->n_troubled = cd->h_status[3];
-        rep->status_cell = flags ? cd->h_status[1] : -1;
+        unsigned long long sum = 0;
+        std::memcpy(&sum, h + 6, sizeof(sum));
+        rep->iters_min = h[4];
+        rep->iters_max = h[5];
+        rep->iters_mean = cd->host.n_cells ? double(sum) / double(cd->host.n_cells) : 0.0;
+        rep->n_troubled = h[3];
+        rep->status_cell = h[0] ? h[1] : -1;
     }
-    if (flags & afe::kStatusNonfinite) return fail(AFE_E_NONFINITE, "non-finite state after the update");
-    if (flags & afe::kStatusNoConv) return fail(AFE_E_NO_CONVERGENCE, "predictor did not converge");
-    if (flags & afe::kStatusPositivity) return fail(AFE_E_POSITIVITY, "density or pressure not positive");
+    const afe_status st = status_of(h[0]);
+    if (st != AFE_OK) return fail(st, status_text(st));
     return AFE_OK;
 }
 
 afe_status afe_profile_enable(afe_cell_data *cd, int32_t enable) {
     if (!cd) return fail(AFE_E_ARG, "null argument");
-    if (enable && !cd->hooks.bytes) {
-        for (int i = 0; i < afe::kSyncEvery; ++i) {
-            HIP_TRY(hipEventCreate(&cd->hooks.start[i]));
-            HIP_TRY(hipEventCreate(&cd->hooks.stop[i]));
-        }
-        HIP_TRY(cd->alloc(cd->hooks.bytes, 1));
-    }
-    cd->prof_on = enable != 0;
-    cd->prof_ms = 0.0;
-    cd->prof_launches = 0;
-    if (cd->hooks.bytes) HIP_TRY(hipMemset(cd->hooks.bytes, 0, sizeof(unsigned long long)));
-    return AFE_OK;
+    return profile_enable(cd->solo, enable);
 }
 
 afe_status afe_profile_read(afe_cell_data *cd, double *kernel_ms, int64_t *launches, double *bytes) {
     if (!cd) return fail(AFE_E_ARG, "null argument");
-    unsigned long long b = 0;
-    if (cd->hooks.bytes) HIP_TRY(hipMemcpy(&b, cd->hooks.bytes, sizeof(b), hipMemcpyDeviceToHost));
-    if (kernel_ms) *kernel_ms = cd->prof_ms;
-    if (launches) *launches = cd->prof_launches;
-    if (bytes) *bytes = double(b);
-    return AFE_OK;
+    return profile_read(cd->solo, kernel_ms, launches, bytes);
 }
 
 afe_status afe_predictor_state(const afe_cell_data *cd, double *q, void *stream) {
@@ -462,6 +853,193 @@ afe_status afe_cell_diagnostics(const afe_cell_data *cd, int32_t *iters, double 
     if (iters) HIP_TRY(hipMemcpy(iters, cd->w.iters, sizeof(int32_t) * cd->host.n_cells, hipMemcpyDeviceToHost));
     if (mu) HIP_TRY(hipMemcpy(mu, cd->w.mu_cell, sizeof(double) * cd->host.n_cells, hipMemcpyDeviceToHost));
     return AFE_OK;
+}
+
+// ----------------------------------------------------------------- batches
+
+afe_status afe_batch_create(afe_batch **out) {
+    if (!out) return fail(AFE_E_ARG, "null argument");
+    *out = new (std::nothrow) afe_batch();
+    if (!*out) return fail(AFE_E_ARG, "out of host memory");
+    return AFE_OK;
+}
+
+void afe_batch_free(afe_batch *b) {
+    if (!b) return;
+    for (afe_cell_data *cd : b->eng.cds)
+        if (cd) cd->batch = nullptr;
+    delete b;
+}
+
+afe_status afe_batch_attach(afe_batch *b, afe_cell_data *cd, double *u, double cfl, int32_t *slot) {
+    if (!b || !cd || !u || !(cfl > 0.0)) return fail(AFE_E_ARG, "invalid argument");
+    if (cd->batch) return fail(AFE_E_ARG, "object already attached to a batch");
+    Engine &E = b->eng;
+    int sl = 0;
+    while (sl < afe::kMaxSlots && E.cds[sl]) ++sl;
+    if (sl == afe::kMaxSlots) return fail(AFE_E_ARG, "batch full");
+    E.cds[sl] = cd;
+    E.u[sl] = u;
+    E.cfl[sl] = cfl;
+    E.dirty = true;
+    cd->batch = b;
+    if (slot) *slot = sl;
+    return AFE_OK;
+}
+
+afe_status afe_batch_detach(afe_batch *b, afe_cell_data *cd) {
+    if (!b || !cd || cd->batch != b) return fail(AFE_E_ARG, "object not in this batch");
+    Engine &E = b->eng;
+    for (int sl = 0; sl < afe::kMaxSlots; ++sl)
+        if (E.cds[sl] == cd) {
+            E.cds[sl] = nullptr;
+            E.u[sl] = nullptr;
+        }
+    E.dirty = true;
+    cd->batch = nullptr;
+    return AFE_OK;
+}
+
+afe_status afe_batch_step(afe_batch *b, afe_batch_report *reps, int32_t n_reps, void *stream) {
+    if (!b || (reps && n_reps < 0)) return fail(AFE_E_ARG, "invalid argument");
+    Engine &E = b->eng;
+    if (E.n_slots() == 0) return AFE_OK;
+    return on_own_stream(E, static_cast<hipStream_t>(stream), [&](hipStream_t s) -> afe_status {
+        AFE_TRY(sync_layout(E, s));
+        return batch_step_on(E, reps, n_reps, s);
+    });
+}
+
+afe_status afe_batch_set_shape(afe_batch *b, const afe_launch_shape *shape) {
+    if (!b || !shape) return fail(AFE_E_ARG, "null argument");
+    if (shape->rounds < 1 || shape->rounds > afe::kMaxRounds || !(shape->sub >= 0.0) || !(shape->minv >= 0.0) ||
+        !(shape->anderson >= 0.0) || shape->sub > 64.0 || shape->minv > 64.0 || shape->anderson > 64.0)
+        return fail(AFE_E_ARG, "launch shape out of range");
+    if (shape->graph && !(shape->sub > 0.0 && shape->minv > 0.0 && shape->anderson > 0.0))
+        return fail(AFE_E_ARG, "graph replay needs persistent grids");
+    Engine &E = b->eng;
+    E.shape = *shape;
+    E.drop_graphs();
+    return AFE_OK;
+}
+
+afe_status afe_batch_get_shape(const afe_batch *b, afe_launch_shape *shape) {
+    if (!b || !shape) return fail(AFE_E_ARG, "null argument");
+    *shape = b->eng.shape;
+    return AFE_OK;
+}
+
+afe_status afe_batch_tune(afe_batch *b, void *stream, afe_launch_shape *chosen) {
+    if (!b) return fail(AFE_E_ARG, "null argument");
+    Engine &E = b->eng;
+    if (E.n_slots() == 0) {
+        if (chosen) *chosen = E.shape;
+        return AFE_OK;
+    }
+    if (E.prof_on) return fail(AFE_E_ARG, "profiling is enabled");
+    return on_own_stream(E, static_cast<hipStream_t>(stream), [&](hipStream_t s) -> afe_status {
+        // every candidate steps a working copy of the states, refreshed from a saved copy
+        std::vector<double *> orig(E.u);
+        std::vector<double *> work(afe::kMaxSlots, nullptr), saved(afe::kMaxSlots, nullptr);
+        size_t total = 0;
+        for (int sl = 0; sl < afe::kMaxSlots; ++sl)
+            if (E.cds[sl]) total += size_t(5) * E.cds[sl]->host.ndof;
+        double *scratch = nullptr;
+        HIP_TRY(hipMalloc(&scratch, 2 * total * sizeof(double)));
+        size_t off = 0;
+        for (int sl = 0; sl < afe::kMaxSlots; ++sl)
+            if (E.cds[sl]) {
+                const size_t n = size_t(5) * E.cds[sl]->host.ndof;
+                saved[sl] = scratch + off;
+                work[sl] = scratch + total + off;
+                off += n;
+            }
+        afe_status st = AFE_OK;
+        for (int sl = 0; sl < afe::kMaxSlots && st == AFE_OK; ++sl)
+            if (E.cds[sl] && hipMemcpyAsync(saved[sl], orig[sl], size_t(5) * E.cds[sl]->host.ndof * sizeof(double),
+                                            hipMemcpyDeviceToDevice, s) != hipSuccess)
+                st = fail(AFE_E_HIP, "state copy");
+        for (int sl = 0; sl < afe::kMaxSlots; ++sl)
+            if (E.cds[sl]) E.u[sl] = work[sl];
+        E.dirty = true;
+        auto time_shape = [&](const afe_launch_shape &sh, double &ms) -> afe_status {
+            E.shape = sh;
+            E.drop_graphs();
+            for (int rep = 0; rep < 2; ++rep) {  // the first run captures graphs and warms caches
+                for (int sl = 0; sl < afe::kMaxSlots; ++sl)
+                    if (E.cds[sl])
+                        HIP_TRY(hipMemcpyAsync(work[sl], saved[sl], size_t(5) * E.cds[sl]->host.ndof * sizeof(double),
+                                               hipMemcpyDeviceToDevice, s));
+                AFE_TRY(sync_layout(E, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                const auto t0 = std::chrono::steady_clock::now();
+                const afe_status r = batch_step_on(E, nullptr, 0, s);
+                if (r != AFE_OK && r != AFE_E_NO_CONVERGENCE && r != AFE_E_POSITIVITY && r != AFE_E_NONFINITE) return r;
+                ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            }
+            return AFE_OK;
+        };
+        afe_launch_shape best{1.0, 1.0, 1.0, 4, 0};  // start: all grids persistent
+        double best_ms = 0.0;
+        if (st == AFE_OK) st = time_shape(best, best_ms);
+        auto trial = [&](afe_launch_shape cand) -> afe_status {
+            if (cand.graph && !(cand.sub > 0.0 && cand.minv > 0.0 && cand.anderson > 0.0)) return AFE_OK;
+            double ms = 0.0;
+            AFE_TRY(time_shape(cand, ms));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand;
+            }
+            return AFE_OK;
+        };
+        const double mults[] = {0.0, 1.0, 2.0, 4.0};
+        for (double m : mults)
+            if (st == AFE_OK && m != best.minv) {
+                afe_launch_shape c = best;
+                c.minv = m;
+                st = trial(c);
+            }
+        for (double m : mults)
+            if (st == AFE_OK && m != best.sub) {
+                afe_launch_shape c = best;
+                c.sub = m;
+                st = trial(c);
+            }
+        for (double m : mults)
+            if (st == AFE_OK && m != best.anderson) {
+                afe_launch_shape c = best;
+                c.anderson = m;
+                st = trial(c);
+            }
+        const int rounds[] = {2, 4, 8, 16};
+        for (int gflag = 0; gflag < 2; ++gflag)
+            for (int r : rounds)
+                if (st == AFE_OK && !(r == best.rounds && gflag == best.graph)) {
+                    afe_launch_shape c = best;
+                    c.rounds = r;
+                    c.graph = gflag;
+                    st = trial(c);
+                }
+        for (int sl = 0; sl < afe::kMaxSlots; ++sl) E.u[sl] = orig[sl];
+        E.dirty = true;
+        E.shape = best;
+        E.drop_graphs();
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(scratch);
+        if (st != AFE_OK) return st;
+        if (chosen) *chosen = best;
+        return AFE_OK;
+    });
+}
+
+afe_status afe_batch_profile_enable(afe_batch *b, int32_t enable) {
+    if (!b) return fail(AFE_E_ARG, "null argument");
+    return profile_enable(b->eng, enable);
+}
+
+afe_status afe_batch_profile_read(afe_batch *b, double *kernel_ms, int64_t *launches, double *bytes) {
+    if (!b) return fail(AFE_E_ARG, "null argument");
+    return profile_read(b->eng, kernel_ms, launches, bytes);
 }
 
 }  // extern "C"

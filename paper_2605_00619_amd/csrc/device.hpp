@@ -59,8 +59,6 @@ struct DevWork {
     double *fprev;   // [ndof][nc] residual G(x) - x of the current iterate
     double *gprev;   // [ndof][nc] G(x) of the current iterate
     double *part;    // [n_cells][tiles of 64 DOFs][2 * 64 + 2] partial dots and norms
-    double *gamma;   // [n_cells][63] Anderson coefficients
-    int32_t *kuse;   // [n_cells] history columns used by the update
     double *dF;      // per cell: depth columns of n_c * nc (append-only)
     double *dG;
     double *gram;    // [n_cells][63][63] Cholesky rows, [n_cells][63][63] Gram, [n_cells][63] scales
@@ -72,22 +70,41 @@ struct DevWork {
     double *mu_cell; // [n_cells]
     double *beta;    // [n_cells]
     double *cflterm; // [n_cells]
-    int32_t *alist;  // [2][n_cells] lists of cells still iterating (ping-pong)
-    int32_t *acount; // [2] their lengths
-    int32_t *iters;  // [n_cells]
-    int32_t *status; // [4]: flags, first bad cell, active count, troubled count
+    int32_t *iters;  // [n_cells] predictor iterations done in this step
+    int32_t *status; // [8]: flags, first bad cell, -, troubled count, iterations min, max, sum (64 bit)
+    double *gamma;   // [n_cells][63] Anderson coefficients
+    int32_t *kuse;   // [n_cells] history columns used by the update
+    double *dt;      // [1] time step of the current step
+    const double *u; // state u^n of the current step, SoA [5][ndof] (caller-owned)
+    double tol;      // predictor stop: max|G(q)-q| <= tol * max(1, max|G(q)|)
+    int max_iter;
     int depth;
 };
 
+// One simulation as seen by the batched predictor kernels.
+struct DevSlot {
+    DevGrid g;
+    DevWork w;
+};
+
+// Entries of the active lists: slot << kSlotShift | cell.
+constexpr int kSlotShift = 24;
+constexpr int kMaxSlots = 64;
+constexpr int kMaxCellsPerSlot = 1 << kSlotShift;
+
 enum : int { kStatusNoConv = 1, kStatusPositivity = 2, kStatusNonfinite = 4 };
 
-// Predictor iterations launched between two reads of the active-cell count.
-constexpr int kSyncEvery = 4;
+// Grid sizes of one predictor iteration's kernels: workgroups of a
+// persistent grid, 0 = one workgroup per work item.
+struct IterShape {
+    int g_sub = 0, g_gather = 0, g_minv = 0, g_dots = 0, g_solve = 0, g_update = 0;
+};
 
-// Events bracketing the launches of the predictor's M^{-1} kernel between two
-// synchronisations, and its algorithmic byte counter.
+// Events bracketing each launch of the predictor's M^{-1} kernel, and its
+// algorithmic byte counter.
+constexpr int kMaxRounds = 16;
 struct ProfileHooks {
-    hipEvent_t start[kSyncEvery], stop[kSyncEvery];
+    hipEvent_t start[kMaxRounds], stop[kMaxRounds];
     unsigned long long *bytes;
 };
 
@@ -96,13 +113,35 @@ hipError_t launch_mass_assemble(const DevGrid &g, hipStream_t s);
 hipError_t launch_mass_invert(const DevGrid &g, hipStream_t s);
 hipError_t launch_prim_to_cons(const DevGrid &g, const double *prim, double *u, hipStream_t s);
 hipError_t launch_detect(const DevGrid &g, const DevWork &w, const double *u, hipStream_t s);
-hipError_t launch_cfl_max(const DevGrid &g, const DevWork &w, double *out, hipStream_t s);
-hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, const double *u, hipStream_t s);
-hipError_t launch_pred_iteration(const DevGrid &g, const DevWork &w, const double *u, double dt, int it,
-                                 int max_iter, double tol, const int32_t *list, const int32_t *count, int n_upper,
-                                 int32_t *next, int32_t *next_count, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
-                                 unsigned long long *bytes);
-hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, double dt, hipStream_t s);
-hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, double dt, hipStream_t s);
+// Time step of eqn.timestep into *w.dt (cfl > 0) from the detector's cell
+// terms; the largest term is also written to *smax.
+hipError_t launch_cfl_dt(const DevGrid &g, const DevWork &w, double cfl, double h_min, double *smax, hipStream_t s);
+hipError_t launch_set_dt(const DevWork &w, double dt, hipStream_t s);
+// Predictor start for one slot: q = u^n at every time node, counters cleared,
+// the slot's cells written to list[base ...].
+hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, int slot, int32_t *list, int64_t base, hipStream_t s);
+hipError_t launch_set_count(int32_t *count, int value, hipStream_t s);
+// One predictor iteration over the listed (slot, cell) entries of one group
+// of slots with the same degree and precision.  n_upper bounds the list
+// length (used when a grid is not persistent); max_cell_dofs and
+// max_cell_subtets are maxima over the group.
+struct RoundArgs {
+    int N, mixed;
+    const DevSlot *tab;
+    const int32_t *list, *count;
+    int32_t *next, *next_count;
+    int n_upper, max_cell_dofs, max_cell_subtets;
+    IterShape shape;
+    hipEvent_t ev0, ev1;
+    unsigned long long *bytes;
+};
+hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s);
+hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, hipStream_t s);
+hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, hipStream_t s);
+// Predictor iteration counts of the step into status[4..7].
+hipError_t launch_step_stats(const DevGrid &g, const DevWork &w, hipStream_t s);
+// Occupancy-derived persistent grid sizes for degree N (workgroups that fit
+// on the device at once, per kernel).
+IterShape resident_shape(int N, int mixed);
 
 }  // namespace afe

@@ -10,6 +10,7 @@
 
 #include <cfloat>
 #include <climits>
+#include <algorithm>
 #include <cmath>
 
 #include "device.hpp"
@@ -260,89 +261,269 @@ __global__ void __launch_bounds__(256) k_detect(DevGrid g, DevWork w, const doub
     }
 }
 
-__global__ void __launch_bounds__(1024) k_cfl_max(int n, const double *__restrict__ term, double *out) {
+// Largest cell term s_max into *smax and, for cfl > 0, the time step
+// dt = cfl h_min / ((2N+1) s_max) into *w.dt; a non-finite or non-positive
+// s_max gives dt = 0 and the non-finite status.  NaN terms propagate.
+__global__ void __launch_bounds__(1024) k_cfl_dt(int n, DevWork w, double *smax, double cfl, double h_min, int n21) {
     __shared__ double red[16];
     double m = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, term[i]);
-    m = wave_max(m);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const double t = w.cflterm[i];
+        m = (t != t || m != m) ? t + m : fmax(m, t);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const double t = __shfl_xor(m, o, kWave);
+        m = (t != t || m != m) ? t + m : fmax(m, t);
+    }
     if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = m;
     __syncthreads();
-    if (threadIdx.x < kWave) {
-        double v = threadIdx.x < blockDim.x / kWave ? red[threadIdx.x] : 0.0;
-        v = wave_max(v);
-        if (threadIdx.x == 0) out[0] = v;
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int i = 0; i < int(blockDim.x) / kWave; ++i) v = (red[i] != red[i] || v != v) ? red[i] + v : fmax(v, red[i]);
+        smax[0] = v;
+        if (cfl > 0.0) {
+            const bool ok = v > 0.0 && isfinite(v);
+            w.dt[0] = ok ? cfl * h_min / (double(n21) * v) : 0.0;
+            if (!ok) atomicOr(&w.status[0], kStatusNonfinite);
+        }
     }
 }
 
 // ------------------------------------------------------------- predictor
+//
+// The iteration kernels run over a list of (slot, cell) entries that may mix
+// cells of several simulations of one degree and precision (a slot is one
+// simulation's DevGrid and DevWork in a device table).  Each kernel is a
+// grid-stride loop over work items, so one launch shape serves every list
+// length: a persistent grid of a fixed number of workgroups, or one
+// workgroup per item.  Logical block L (xcd_block) takes items L, L + G, ...,
+// so the consecutive items of one cell run on one XCD and share its L2.
+
+// Pointers read from the slot table are generic; the M^{-1} kernels restate
+// them in the global address space (the streamed matrix) and in the constant
+// address space (the right-hand side, read-only during the kernel and
+// wave-uniform, so it is fetched with scalar loads).
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T *;
+
+// Wave-uniform copies (the value of lane 0) of values that are uniform but
+// that the compiler cannot prove so.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uni64(int64_t v) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(v) >> 32))));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+template <typename T>
+__device__ inline T *uni_ptr(T *p) {
+    return reinterpret_cast<T *>(uni64(reinterpret_cast<int64_t>(p)));
+}
+
+__device__ inline void decode(int32_t e, int &slot, int &c) {
+    slot = e >> kSlotShift;
+    c = e & (kMaxCellsPerSlot - 1);
+}
 
 template <int N>
-__global__ void k_pred_init(DevGrid g, DevWork w, const double *__restrict__ u) {
+__global__ void k_pred_init(DevGrid g, DevWork w, int slot, int32_t *list, int64_t base) {
     constexpr int nc = Dim<N>::nc, nt = Dim<N>::nt;
     const int64_t l = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (l < g.ndof)
         for (int a = 0; a < nt; ++a)
-            for (int v = 0; v < 5; ++v) w.x[l * nc + a * 5 + v] = u[v * g.ndof + l];
-    if (l == 0) w.acount[0] = g.n_cells;
+            for (int v = 0; v < 5; ++v) w.x[l * nc + a * 5 + v] = w.u[v * g.ndof + l];
     if (l < g.n_cells) {
-        w.alist[l] = int32_t(l);
+        list[base + l] = (slot << kSlotShift) | int32_t(l);
         w.iters[l] = 0;
         w.hist[2 * l] = 0;
         w.hist[2 * l + 1] = 0;
     }
 }
 
-__global__ void k_zero_int(int32_t *p) {
-    if (threadIdx.x == 0) p[0] = 0;
+__global__ void k_set_int(int32_t *p, int v) {
+    if (threadIdx.x == 0) p[0] = v;
 }
 
-// Per sub-tet and time node: nodal flux, contravariant transform
-// f*_d = dt sum_x G[d][x] F_x (eq:modified_fluxes), and the reference stiffness
-// contraction r[a][m] = w_a |J| sum_d sum_p K^_d[m][p] f*_d[a][p] (eq:ader4).
-// POST = true instead forms the time integrals of the converged predictor:
+__global__ void k_set_double(double *p, double v) {
+    if (threadIdx.x == 0) p[0] = v;
+}
+
+// Nodal flux of the Navier-Stokes equations at node m of a sub-tet for one
+// time node (gradient from the reference derivatives when mu_c != 0) and its
+// contravariant form f*_d = dt sum_x G[d][x] F_x (eq:modified_fluxes).
+template <int N>
+__device__ inline void node_flux(const double *Ds, const double (*qn)[5], int m, const double G[9], const double q[5],
+                                 double gamma, double mu_c, double dt, double *fstar, double F[3][5]) {
+    constexpr int np = Dim<N>::np;
+    double gq[3][5] = {};
+    if (mu_c != 0.0) {
+        double rg[3][5] = {};
+        for (int d = 0; d < 3; ++d)
+            for (int p = 0; p < np; ++p) {
+                const double dd = Ds[(d * np + m) * np + p];
+                for (int v = 0; v < 5; ++v) rg[d][v] += dd * qn[p][v];
+            }
+        for (int x = 0; x < 3; ++x)
+            for (int v = 0; v < 5; ++v) gq[x][v] = G[0 * 3 + x] * rg[0][v] + G[1 * 3 + x] * rg[1][v] + G[2 * 3 + x] * rg[2][v];
+    }
+    ns_flux(q, gq, gamma, mu_c, F);
+    for (int d = 0; d < 3; ++d)
+        for (int v = 0; v < 5; ++v)
+            fstar[d * 5 + v] = dt * (G[d * 3 + 0] * F[0][v] + G[d * 3 + 1] * F[1][v] + G[d * 3 + 2] * F[2][v]);
+}
+
+// Work item = (entry, chunk of spb sub-tets of the cell).  Per sub-tet and
+// time node: nodal flux and the reference stiffness contraction
+// rk[a][m] = w_a |J| sum_d sum_p K^_d[m][p] f*_d[a][p] (eq:ader4); in mixed
+// precision the sub-tet's part of (K_tau (x) M_i)(q - 1 (x) u^n) is added,
+// which makes rk the unpreconditioned residual of eq:ADER-localCauchy.
+// Block 0 clears the next list's length.
+template <int N>
+__global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_per_eu(2))) k_round_subtet(const DevSlot *__restrict__ tab,
+                                                                   const int32_t *__restrict__ list,
+                                                                   const int32_t *__restrict__ count, int chunks,
+                                                                   int32_t *next_count) {
+    constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
+    __shared__ double Ks[3 * np * np];
+    __shared__ double Ds[3 * np * np];
+    __shared__ double Ms[np * np];
+    __shared__ double qs[spb][nt][np][5];
+    __shared__ double fs[spb][nt][np][15];
+    __shared__ double us[spb][np][5];
+    __shared__ double mt[spb][nt][np][5];  // M^ (q_b - u^n) per time node
+    if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
+    const int tid = threadIdx.x;
+    const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
+    const int n_items = *count * chunks;
+    bool loaded = false;
+    for (int item = xcd_block(); item < n_items; item += gridDim.x) {
+        int slot, c;
+        decode(list[item / chunks], slot, c);
+        const DevGrid &g = tab[slot].g;
+        const DevWork &w = tab[slot].w;
+        const int64_t s0 = g.sub_ptr[c], s1 = g.sub_ptr[c + 1];
+        const int nchunk = int((s1 - s0 + spb - 1) / spb);
+        const int chunk = item % chunks;
+        if (chunk >= nchunk) continue;
+        const bool mixed = g.mixed != 0;
+        if (!loaded) {
+            for (int t = tid; t < np * np; t += blockDim.x) Ms[t] = g.ref->M[t];
+            for (int t = tid; t < 3 * np * np; t += blockDim.x) {
+                Ks[t] = g.ref->K[t];
+                Ds[t] = g.ref->D[t];
+            }
+            loaded = true;
+        }
+        const int64_t k = s0 + int64_t(chunk) * spb + s;
+        const bool valid = (s < spb) && (k < s1);
+        const double dt = *w.dt;
+        double G[9], dj = 0.0, mu_c = 0.0;
+        double q[5] = {1, 0, 0, 0, 1};
+        if (valid) {
+            for (int i = 0; i < 9; ++i) G[i] = g.geo[k * 10 + i];
+            dj = g.geo[k * 10 + 9];
+            mu_c = w.mu_cell[c];
+            const int64_t l = g.dof_ptr[c] + g.conn[k * np + m];
+            for (int v = 0; v < 5; ++v) {
+                q[v] = w.x[l * nc + a * 5 + v];
+                qs[s][a][m][v] = q[v];
+            }
+            if (mixed && a == 0)
+                for (int v = 0; v < 5; ++v) us[s][m][v] = w.u[v * g.ndof + l];
+        }
+        __syncthreads();
+        if (valid) {
+            double F[3][5];
+            node_flux<N>(Ds, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
+        }
+        if (mixed) {
+            __syncthreads();
+            // thread (s, b = a, m): the sub-tet mass product of time node b
+            double t[5] = {0, 0, 0, 0, 0};
+            if (valid)
+                for (int p = 0; p < np; ++p) {
+                    const double mm = Ms[m * np + p];
+                    for (int v = 0; v < 5; ++v) t[v] += mm * (qs[s][a][p][v] - us[s][p][v]);
+                }
+            for (int v = 0; v < 5; ++v) mt[s < spb ? s : 0][a][m][v] = valid ? t[v] : 0.0;
+        }
+        __syncthreads();
+        if (valid) {
+            double r[5] = {0, 0, 0, 0, 0};
+            for (int d = 0; d < 3; ++d)
+                for (int p = 0; p < np; ++p) {
+                    const double kk = Ks[(d * np + m) * np + p];
+                    for (int v = 0; v < 5; ++v) r[v] += kk * fs[s][a][p][d * 5 + v];
+                }
+            const double sc = g.ref->w[a] * dj;
+            double *out = w.rk + (k * np + m) * nc + a * 5;
+            if (mixed) {
+                double mr[5] = {0, 0, 0, 0, 0};
+                for (int b = 0; b < nt; ++b) {
+                    const double kt = g.ref->Ktau[a * nt + b];
+                    for (int v = 0; v < 5; ++v) mr[v] += kt * mt[s][b][m][v];
+                }
+                for (int v = 0; v < 5; ++v) out[v] = sc * r[v] + dj * mr[v];
+            } else {
+                for (int v = 0; v < 5; ++v) out[v] = sc * r[v];
+            }
+        }
+        __syncthreads();  // LDS is rewritten by the next item
+    }
+}
+
+// Assembly R[l][col] = sum over the DOF's ascending incidence list of the
+// sub-tet contributions rk (mixed: the FP32 scaled residual D R); work item
+// = (entry, 256 consecutive elements of the cell's DOF-major block).
+template <int N>
+__global__ void __launch_bounds__(256) k_round_gather(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ count, int per) {
+    constexpr int nc = Dim<N>::nc;
+    const int n_items = *count * per;
+    for (int item = xcd_block(); item < n_items; item += gridDim.x) {
+        int slot, c;
+        decode(list[item / per], slot, c);
+        const DevGrid &g = tab[slot].g;
+        const DevWork &w = tab[slot].w;
+        const int64_t d0 = g.dof_ptr[c];
+        const int64_t e = int64_t(item % per) * blockDim.x + threadIdx.x;
+        if (e >= (g.dof_ptr[c + 1] - d0) * nc) continue;
+        const int64_t t = d0 * nc + e;
+        const int64_t l = t / nc;
+        const int col = int(t % nc);
+        double acc = 0.0;
+        for (int q = g.inc_ptr[l]; q < g.inc_ptr[l + 1]; ++q) acc += w.rk[int64_t(g.inc_idx[q]) * nc + col];
+        if (g.mixed)
+            w.R32[t] = float(acc * g.dscale[l]);
+        else
+            w.R[t] = acc;
+    }
+}
+
+// Time integrals of the converged predictor, all sub-tets of one simulation:
 // the volume term |J| sum_d V^_d F*bar_d (Sec. 4.4) and the face traces
 // (qbar, Fbar) at the boundary-triangle nodes.
-template <int N, bool POST>
-__global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w, double dt,
-                                                             const int32_t *__restrict__ list,
-                                                             const int32_t *__restrict__ count, int chunks,
-                                                             const double *__restrict__ u) {
+template <int N>
+__global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevWork w) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr int nf = Dim<N>::nf;
     __shared__ double Ks[3 * np * np];
     __shared__ double Ds[3 * np * np];
     __shared__ double qs[spb][nt][np][5];
     __shared__ double fs[spb][nt][np][15];
-    __shared__ double Fs[POST ? spb : 1][POST ? nt : 1][POST ? np : 1][15];
-    __shared__ double fbar[POST ? spb : 1][POST ? np : 1][15];
-    // mixed precision: u^n at the sub-tet nodes and M^ for the mass term
-    __shared__ double us[POST ? 1 : spb][POST ? 1 : np][5];
-    __shared__ double Ms[POST ? 1 : np * np];
-    __shared__ double mt[POST ? 1 : spb][POST ? 1 : nt][POST ? 1 : np][5];  // M^ (q_b - u^n) per time node
+    __shared__ double Fs[spb][nt][np][15];
+    __shared__ double fbar[spb][np][15];
     const int tid = threadIdx.x;
-    const bool mixed = !POST && g.mixed;
-    if (mixed)
-        for (int t = tid; t < np * np; t += blockDim.x) Ms[POST ? 0 : t] = g.ref->M[t];
     for (int t = tid; t < 3 * np * np; t += blockDim.x) {
         Ks[t] = g.ref->K[t];
         Ds[t] = g.ref->D[t];
     }
     const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
-    int64_t k;
-    bool valid;
-    int c = 0;
-    if (POST) {
-        k = int64_t(blockIdx.x) * spb + s;
-        valid = (s < spb) && (k < g.nsub);
-        if (valid) c = g.sub_cell[k];
-    } else {
-        // block -> (active cell, chunk of spb of its sub-tets)
-        const int lb = xcd_block();
-        if (lb / chunks >= *count) return;  // the list shrank since the launch was sized
-        c = list[lb / chunks];
-        k = g.sub_ptr[c] + int64_t(lb % chunks) * spb + s;
-        valid = (s < spb) && (k < g.sub_ptr[c + 1]);
-    }
+    const int64_t k = int64_t(blockIdx.x) * spb + s;
+    const bool valid = (s < spb) && (k < g.nsub);
+    const int c = valid ? g.sub_cell[k] : 0;
+    const double dt = *w.dt;
     double G[9], dj = 0.0, mu_c = 0.0;
     double q[5] = {1, 0, 0, 0, 1};
     if (valid) {
@@ -354,73 +535,20 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
             q[v] = w.x[l * nc + a * 5 + v];
             qs[s][a][m][v] = q[v];
         }
-        if (mixed && a == 0)
-            for (int v = 0; v < 5; ++v) us[POST ? 0 : s][POST ? 0 : m][v] = u[v * g.ndof + l];
     }
     __syncthreads();
     if (valid) {
-        double gq[3][5] = {};
-        if (mu_c != 0.0) {
-            double rg[3][5] = {};
-            for (int d = 0; d < 3; ++d)
-                for (int p = 0; p < np; ++p) {
-                    const double dd = Ds[(d * np + m) * np + p];
-                    for (int v = 0; v < 5; ++v) rg[d][v] += dd * qs[s][a][p][v];
-                }
-            for (int x = 0; x < 3; ++x)
-                for (int v = 0; v < 5; ++v) gq[x][v] = G[0 * 3 + x] * rg[0][v] + G[1 * 3 + x] * rg[1][v] + G[2 * 3 + x] * rg[2][v];
-        }
         double F[3][5];
-        ns_flux(q, gq, g.gamma, mu_c, F);
-        for (int d = 0; d < 3; ++d)
-            for (int v = 0; v < 5; ++v)
-                fs[s][a][m][d * 5 + v] = dt * (G[d * 3 + 0] * F[0][v] + G[d * 3 + 1] * F[1][v] + G[d * 3 + 2] * F[2][v]);
-        if (POST)
-            for (int x = 0; x < 3; ++x)
-                for (int v = 0; v < 5; ++v) Fs[POST ? s : 0][POST ? a : 0][POST ? m : 0][x * 5 + v] = F[x][v];
-    }
-    if (mixed) {
-        __syncthreads();
-        // thread (s, b = a, m): the sub-tet mass product of time node b
-        double t[5] = {0, 0, 0, 0, 0};
-        if (valid)
-            for (int p = 0; p < np; ++p) {
-                const double mm = Ms[POST ? 0 : m * np + p];
-                for (int v = 0; v < 5; ++v) t[v] += mm * (qs[s][a][p][v] - us[POST ? 0 : s][POST ? 0 : p][v]);
-            }
-        for (int v = 0; v < 5; ++v) mt[POST ? 0 : s][POST ? 0 : a][POST ? 0 : m][v] = t[v];
+        node_flux<N>(Ds, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
+        for (int x = 0; x < 3; ++x)
+            for (int v = 0; v < 5; ++v) Fs[s][a][m][x * 5 + v] = F[x][v];
     }
     __syncthreads();
-    if (!POST) {
-        if (!valid) return;
-        double r[5] = {0, 0, 0, 0, 0};
-        for (int d = 0; d < 3; ++d)
-            for (int p = 0; p < np; ++p) {
-                const double kk = Ks[(d * np + m) * np + p];
-                for (int v = 0; v < 5; ++v) r[v] += kk * fs[s][a][p][d * 5 + v];
-            }
-        const double sc = g.ref->w[a] * dj;
-        double *out = w.rk + (k * np + m) * nc + a * 5;
-        if (mixed) {
-            // unpreconditioned residual of eq:ADER-localCauchy: add the sub-tet's part
-            // of (K_tau (x) M_i)(q - 1 (x) u^n)
-            double mr[5] = {0, 0, 0, 0, 0};
-            for (int b = 0; b < nt; ++b) {
-                const double kt = g.ref->Ktau[a * nt + b];
-                for (int v = 0; v < 5; ++v) mr[v] += kt * mt[POST ? 0 : s][POST ? 0 : b][POST ? 0 : m][v];
-            }
-            for (int v = 0; v < 5; ++v) out[v] = sc * r[v] + dj * mr[v];
-        } else {
-            for (int v = 0; v < 5; ++v) out[v] = sc * r[v];
-        }
-        return;
-    }
-    // POST: time integrals
     if (valid && a == 0) {
         for (int i = 0; i < 15; ++i) {
             double acc = 0.0;
             for (int b = 0; b < nt; ++b) acc += g.ref->w[b] * fs[s][b][m][i];
-            fbar[POST ? s : 0][POST ? m : 0][i] = acc;
+            fbar[s][m][i] = acc;
         }
     }
     __syncthreads();
@@ -431,7 +559,7 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
         for (int d = 0; d < 3; ++d)
             for (int p = 0; p < np; ++p) {
                 const double kk = Ks[(d * np + p) * np + m];
-                for (int v = 0; v < 5; ++v) r[v] += kk * fbar[POST ? s : 0][p][d * 5 + v];
+                for (int v = 0; v < 5; ++v) r[v] += kk * fbar[s][p][d * 5 + v];
             }
         double *out = w.vk + (k * np + m) * 5;
         for (int v = 0; v < 5; ++v) out[v] = dj * r[v];
@@ -447,57 +575,27 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet(DevGrid g, DevWork w
             }
             for (int i = 0; i < 15; ++i) {
                 double acc = 0.0;
-                for (int b = 0; b < nt; ++b) acc += g.ref->w[b] * Fs[POST ? s : 0][POST ? b : 0][POST ? mm : 0][i];
+                for (int b = 0; b < nt; ++b) acc += g.ref->w[b] * Fs[s][b][mm][i];
                 out[5 + i] = dt * acc;
             }
         }
     }
 }
 
-// R[l][col] = sum over the DOF's incidence list of the sub-tet contributions;
-// blocks cover the DOF-major blocks of the listed cells.
-template <int N>
-__global__ void __launch_bounds__(256) k_gather(DevGrid g, DevWork w, const int32_t *__restrict__ list,
-                                                 const int32_t *__restrict__ count, int per) {
-    constexpr int nc = Dim<N>::nc;
-    const int lb = xcd_block();
-    if (lb / per >= *count) return;
-    const int c = list[lb / per];
-    const int64_t d0 = g.dof_ptr[c];
-    const int64_t e = int64_t(lb % per) * blockDim.x + threadIdx.x;
-    if (e >= (g.dof_ptr[c + 1] - d0) * nc) return;
-    const int64_t t = d0 * nc + e;
-    const int64_t l = t / nc;
-    const int col = int(t % nc);
-    double acc = 0.0;
-    for (int q = g.inc_ptr[l]; q < g.inc_ptr[l + 1]; ++q) acc += w.rk[int64_t(g.inc_idx[q]) * nc + col];
-    if (g.mixed)
-        w.R32[t] = float(acc * g.dscale[l]);
-    else
-        w.R[t] = acc;
-}
-
-// Y = M_i^{-1} X for the listed cells (list == nullptr: all cells), X and Y
-// DOF-major with NC columns.  A block of 4 waves owns 64 rows of one cell; the
-// waves split the inner index j into 4 contiguous ranges and their partial
-// sums are added in wave order through LDS (deterministic).  M_i^{-1} is
-// symmetric, so row j of the stored matrix supplies column j: one j is a
-// coalesced 512-byte load across the wave, and X[j][:] is wave-uniform.
+// Y = M_i^{-1} X for rows [64 tile, 64 tile + 64) of cell c; X and Y DOF-major
+// with NC columns.  The 4 waves of the block split the inner index j into 4
+// contiguous ranges; their partial sums are added in a fixed wave order
+// through LDS (deterministic).  M_i^{-1} is symmetric, so row j of the stored
+// matrix supplies column j: one j is a coalesced 512-byte load across the
+// wave, and X[j][:] is wave-uniform.
 // MODE 0: Y = S (predictor);  MODE 1: add Y into the SoA state u (corrector).
 template <int NC, int MODE>
-__global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restrict__ list,
-                                               const int32_t *__restrict__ count, const double *__restrict__ X,
-                                               double *__restrict__ Y, int tpc, unsigned long long *bytes) {
-    __shared__ double part[3][NC][kWave];
+__device__ inline void minv_tile(const DevGrid &g, int c, int tile, const double *__restrict__ X,
+                                 double *__restrict__ Y, unsigned long long *bytes, double (*part)[kWave]) {
     const int lane = threadIdx.x % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int lb = xcd_block();
-    const int ci = lb / tpc;
-    const int tile = lb % tpc;
-    if (count != nullptr && ci >= *count) return;
-    const int c = list ? list[ci] : ci;
-    const int64_t d0 = g.dof_ptr[c];
-    const int n = int(g.dof_ptr[c + 1] - d0);
+    const int64_t d0 = uni64(g.dof_ptr[c]);
+    const int n = uni(int(g.dof_ptr[c + 1] - d0));
     const int64_t ld = minv_ld(n);
     const int r0 = tile * kWave;
     if (r0 >= n) return;
@@ -508,8 +606,8 @@ __global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restri
     const int row = r0 + lane;
     const bool ok = row < n;
     const int rowc = ok ? row : n - 1;  // clamped: out-of-range lanes read a valid address
-    const double *__restrict__ A = g.minv + g.minv_ptr[c] + rowc;
-    const double *__restrict__ B = X + d0 * NC;
+    const gptr<double> A = (gptr<double>)(uni_ptr(g.minv + g.minv_ptr[c]) + rowc);
+    const cptr<double> B = (cptr<double>)uni_ptr(X + d0 * NC);
     const int span = (n + 3) / 4;
     const int j0 = min(n, wv * span), j1 = min(n, j0 + span);
     double acc[NC];
@@ -519,7 +617,7 @@ __global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restri
     for (; j + 4 <= j1; j += 4) {
         const double m0 = A[int64_t(j) * ld], m1 = A[int64_t(j + 1) * ld];
         const double m2 = A[int64_t(j + 2) * ld], m3 = A[int64_t(j + 3) * ld];
-        const double *b = B + int64_t(j) * NC;
+        const cptr<double> b = B + int64_t(j) * NC;
 #pragma unroll
         for (int col = 0; col < NC; ++col) acc[col] = fma(m0, b[col], acc[col]);
 #pragma unroll
@@ -531,19 +629,23 @@ __global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restri
     }
     for (; j < j1; ++j) {
         const double m0 = A[int64_t(j) * ld];
-        const double *b = B + int64_t(j) * NC;
+        const cptr<double> b = B + int64_t(j) * NC;
 #pragma unroll
         for (int col = 0; col < NC; ++col) acc[col] = fma(m0, b[col], acc[col]);
     }
-    if (wv > 0) {
+    // partial sums added wave 3, 2, 1, 0 through one LDS buffer (10 KB at
+    // NC = 20, so LDS does not cap the number of resident blocks)
+    for (int s = 3; s >= 1; --s) {
+        if (wv == s) {
 #pragma unroll
-        for (int col = 0; col < NC; ++col) part[wv - 1][col][lane] = acc[col];
+            for (int col = 0; col < NC; ++col) part[col][lane] = s == 3 ? acc[col] : part[col][lane] + acc[col];
+        }
+        __syncthreads();
     }
-    __syncthreads();
     if (wv == 0 && ok) {
 #pragma unroll
         for (int col = 0; col < NC; ++col) {
-            const double v = ((acc[col] + part[0][col][lane]) + part[1][col][lane]) + part[2][col][lane];
+            const double v = part[col][lane] + acc[col];
             if (MODE == 0)
                 Y[(d0 + row) * NC + col] = v;
             else
@@ -552,72 +654,103 @@ __global__ void __launch_bounds__(256) k_minv(DevGrid g, const int32_t *__restri
     }
 }
 
-// Mixed precision: S = D (A32 (D R)) with the FP32 scaled inverse A32 and the
-// FP32 right-hand side X32 = D R (written by the gather); FP32 accumulation,
-// result scaled back to FP64.  Same tiling as k_minv.
+// Predictor: S = M_i^{-1} R for the listed cells, work item = (entry, tile).
 template <int NC>
-__global__ void __launch_bounds__(256) k_minv_f32(DevGrid g, const int32_t *__restrict__ list,
-                                                   const int32_t *__restrict__ count, const float *__restrict__ X,
-                                                   double *__restrict__ Y, int tpc, unsigned long long *bytes) {
-    __shared__ float part[3][NC][kWave];
+__global__ void __launch_bounds__(256) k_round_minv(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
+                                                    const int32_t *__restrict__ count, int tpc,
+                                                    unsigned long long *bytes) {
+    __shared__ double part[NC][kWave];
+    const int n_items = *count * tpc;
+    for (int item = xcd_block(); item < n_items; item += gridDim.x) {
+        int slot, c;
+        decode(uni(list[item / tpc]), slot, c);
+        const DevSlot &sl = tab[slot];
+        minv_tile<NC, 0>(sl.g, c, item % tpc, sl.w.R, sl.w.S, bytes, part);
+        __syncthreads();
+    }
+}
+
+// Corrector: u += M_i^{-1} rhs for every cell of one simulation.
+template <int NC>
+__global__ void __launch_bounds__(256) k_minv_update(DevGrid g, const double *__restrict__ X, double *__restrict__ Y,
+                                                     int tpc) {
+    __shared__ double part[NC][kWave];
+    const int lb = xcd_block();
+    minv_tile<NC, 1>(g, lb / tpc, lb % tpc, X, Y, nullptr, part);
+}
+
+// Mixed precision: S = D (A32 (D R)) with the FP32 scaled inverse A32 and the
+// FP32 right-hand side X32 = D R (written by the assembly); FP32
+// accumulation, result scaled back to FP64.  Same tiling as minv_tile.
+template <int NC>
+__global__ void __launch_bounds__(256) k_round_minv32(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ count, int tpc,
+                                                      unsigned long long *bytes) {
+    __shared__ float part[NC][kWave];
     const int lane = threadIdx.x % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int lb = xcd_block();
-    const int ci = lb / tpc;
-    const int tile = lb % tpc;
-    if (ci >= *count) return;
-    const int c = list[ci];
-    const int64_t d0 = g.dof_ptr[c];
-    const int n = int(g.dof_ptr[c + 1] - d0);
-    const int64_t ld = minv32_ld(n);
-    const int r0 = tile * kWave;
-    if (r0 >= n) return;
-    if (bytes != nullptr && threadIdx.x == 0) {
-        const unsigned long long rows = unsigned(min(kWave, n - r0));
-        atomicAdd(bytes, 4ull * rows * unsigned(n) + 8ull * rows * NC + (tile == 0 ? 4ull * unsigned(n) * NC : 0ull));
-    }
-    const int row = r0 + lane;
-    const bool ok = row < n;
-    const int rowc = ok ? row : n - 1;
-    const float *__restrict__ A = g.minv32 + g.minv32_ptr[c] + rowc;
-    const float *__restrict__ B = X + d0 * NC;
-    const int span = (n + 3) / 4;
-    const int j0 = min(n, wv * span), j1 = min(n, j0 + span);
-    float acc[NC];
-#pragma unroll
-    for (int col = 0; col < NC; ++col) acc[col] = 0.0f;
-    int j = j0;
-    for (; j + 4 <= j1; j += 4) {
-        const float m0 = A[int64_t(j) * ld], m1 = A[int64_t(j + 1) * ld];
-        const float m2 = A[int64_t(j + 2) * ld], m3 = A[int64_t(j + 3) * ld];
-        const float *b = B + int64_t(j) * NC;
-#pragma unroll
-        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m0, b[col], acc[col]);
-#pragma unroll
-        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m1, b[NC + col], acc[col]);
-#pragma unroll
-        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m2, b[2 * NC + col], acc[col]);
-#pragma unroll
-        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m3, b[3 * NC + col], acc[col]);
-    }
-    for (; j < j1; ++j) {
-        const float m0 = A[int64_t(j) * ld];
-        const float *b = B + int64_t(j) * NC;
-#pragma unroll
-        for (int col = 0; col < NC; ++col) acc[col] = fmaf(m0, b[col], acc[col]);
-    }
-    if (wv > 0) {
-#pragma unroll
-        for (int col = 0; col < NC; ++col) part[wv - 1][col][lane] = acc[col];
-    }
-    __syncthreads();
-    if (wv == 0 && ok) {
-        const double sc = g.dscale[d0 + row];
-#pragma unroll
-        for (int col = 0; col < NC; ++col) {
-            const float v = ((acc[col] + part[0][col][lane]) + part[1][col][lane]) + part[2][col][lane];
-            Y[(d0 + row) * NC + col] = sc * double(v);
+    const int n_items = *count * tpc;
+    for (int item = xcd_block(); item < n_items; item += gridDim.x) {
+        int slot, c;
+        decode(uni(list[item / tpc]), slot, c);
+        const DevGrid &g = tab[slot].g;
+        const DevWork &w = tab[slot].w;
+        const int tile = item % tpc;
+        const int64_t d0 = uni64(g.dof_ptr[c]);
+        const int n = uni(int(g.dof_ptr[c + 1] - d0));
+        const int64_t ld = minv32_ld(n);
+        const int r0 = tile * kWave;
+        if (r0 >= n) continue;
+        if (bytes != nullptr && threadIdx.x == 0) {
+            const unsigned long long rows = unsigned(min(kWave, n - r0));
+            atomicAdd(bytes, 4ull * rows * unsigned(n) + 8ull * rows * NC + (tile == 0 ? 4ull * unsigned(n) * NC : 0ull));
         }
+        const int row = r0 + lane;
+        const bool ok = row < n;
+        const int rowc = ok ? row : n - 1;
+        const gptr<float> A = (gptr<float>)(uni_ptr(g.minv32 + g.minv32_ptr[c]) + rowc);
+        const cptr<float> B = (cptr<float>)uni_ptr(w.R32 + d0 * NC);
+        const int span = (n + 3) / 4;
+        const int j0 = min(n, wv * span), j1 = min(n, j0 + span);
+        float acc[NC];
+#pragma unroll
+        for (int col = 0; col < NC; ++col) acc[col] = 0.0f;
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+            const float m0 = A[int64_t(j) * ld], m1 = A[int64_t(j + 1) * ld];
+            const float m2 = A[int64_t(j + 2) * ld], m3 = A[int64_t(j + 3) * ld];
+            const cptr<float> b = B + int64_t(j) * NC;
+#pragma unroll
+            for (int col = 0; col < NC; ++col) acc[col] = fmaf(m0, b[col], acc[col]);
+#pragma unroll
+            for (int col = 0; col < NC; ++col) acc[col] = fmaf(m1, b[NC + col], acc[col]);
+#pragma unroll
+            for (int col = 0; col < NC; ++col) acc[col] = fmaf(m2, b[2 * NC + col], acc[col]);
+#pragma unroll
+            for (int col = 0; col < NC; ++col) acc[col] = fmaf(m3, b[3 * NC + col], acc[col]);
+        }
+        for (; j < j1; ++j) {
+            const float m0 = A[int64_t(j) * ld];
+            const cptr<float> b = B + int64_t(j) * NC;
+#pragma unroll
+            for (int col = 0; col < NC; ++col) acc[col] = fmaf(m0, b[col], acc[col]);
+        }
+        for (int s = 3; s >= 1; --s) {
+            if (wv == s) {
+#pragma unroll
+                for (int col = 0; col < NC; ++col) part[col][lane] = s == 3 ? acc[col] : part[col][lane] + acc[col];
+            }
+            __syncthreads();
+        }
+        if (wv == 0 && ok) {
+            const double sc = g.dscale[d0 + row];
+#pragma unroll
+            for (int col = 0; col < NC; ++col) {
+                const float v = part[col][lane] + acc[col];
+                w.S[(d0 + row) * NC + col] = sc * double(v);
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -625,21 +758,22 @@ __global__ void __launch_bounds__(256) k_minv_f32(DevGrid g, const int32_t *__re
 // K_1^{-1} = K_tau^{-1} (x) M_i^{-1}): G(x) = u - (K_tau^{-1} (x) I) S with
 // S = M_i^{-1} R(x), residual f = G(x) - x, and x <- G(x) - dG gamma with
 // gamma = argmin |f - dF gamma|.  Three kernels per iteration:
-//   k_and_dots   (blocks of 64 DOFs of each listed cell): G, f, the new
-//                difference pair into the ring, partial dot products of the
-//                history with the new column and with f, partial max norms;
-//   k_and_solve  (one wave per listed cell): reduces the partials in tile
-//                order, tests convergence, extends (or rebuilds after dropping
-//                the oldest pairs) the Jacobi-scaled Cholesky factor of the
-//                Gram matrix of dF, solves for gamma, builds the next list;
-//   k_and_update (blocks of 64 DOFs): x <- G(x) - sum_j gamma_j dG_j.
+//   k_round_dots   (item = entry, tile of 64 DOFs): G, f, the new difference
+//                  pair into the ring, partial dot products of the history
+//                  with the new column and with f, partial max norms;
+//   k_round_solve  (one wave per entry): reduces the partials in tile order,
+//                  tests convergence, extends (or rebuilds after dropping the
+//                  oldest pairs) the Jacobi-scaled Cholesky factor of the
+//                  Gram matrix of dF, solves for gamma, builds the next list;
+//   k_round_update (item = entry, tile): x <- G(x) - sum_j gamma_j dG_j.
 // Difference pairs live in a ring of `depth` slots, logical order oldest
 // first; a column adding no new direction is not appended; when the ring is
 // full the 8 oldest pairs are dropped.  Depth 0 is the plain fixed-point map.
+// The iteration count of a cell is w.iters[c] (iterations done so far).
 constexpr int kDrop = 8;
 constexpr int kPartStride = 2 * (kMaxDepth + 1) + 2;
 
-// history bookkeeping shared by the three kernels: (count kept, head slot)
+// history bookkeeping: (count kept, head slot) after the drop this iteration makes
 __device__ inline void ring_state(const DevWork &w, int c, int &k, int &head, bool &dropped) {
     k = w.hist[2 * c];
     head = k == 0 ? 0 : w.hist[2 * c + 1];
@@ -652,23 +786,18 @@ __device__ inline void ring_state(const DevWork &w, int c, int &k, int &head, bo
     }
 }
 
+// Tiles of 64 DOFs per cell in the partials buffer of a simulation.
+__device__ inline int part_tiles(const DevGrid &g) { return (g.max_cell_dofs + 63) / 64; }
+
 template <int N>
-__global__ void __launch_bounds__(256) k_and_dots(DevGrid g, DevWork w, const double *__restrict__ u, int it,
-                                                  const int32_t *__restrict__ list, const int32_t *__restrict__ count,
-                                                  int tpc) {
+__device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, int tile, double (*accs)[4]) {
     constexpr int nc = Dim<N>::nc, nt = Dim<N>::nt;
     constexpr int kPer = (64 * nc + 255) / 256;  // elements per thread
-    __shared__ double accs[2 * (kMaxDepth + 1) + 2][4];
-    const int lb = xcd_block();
-    if (lb / tpc >= *count) return;
-    const int c = list[lb / tpc];
-    const int tile = lb % tpc;
     const int64_t d0 = g.dof_ptr[c];
     const int n = int(g.dof_ptr[c + 1] - d0);
-    if (tile * 64 >= n) return;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int depth = w.depth;
-    const bool hist_on = depth > 0 && it > 0;
+    const bool hist_on = depth > 0 && w.iters[c] > 0;
     int k = 0, head = 0;
     bool dropped = false;
     if (hist_on) ring_state(w, c, k, head, dropped);
@@ -697,7 +826,7 @@ __global__ void __launch_bounds__(256) k_and_dots(DevGrid g, DevWork w, const do
             for (int a = 0; a < nt; ++a) acc += g.ref->Ktau_inv[b * nt + a] * sr[a * 5];
             const double xv = w.x[base + e];
             // FP64: G = u^n - ..., mixed: G = x - ... with S from the residual
-            const double gv = (g.mixed ? xv : u[v * g.ndof + d0 + l]) - acc;
+            const double gv = (g.mixed ? xv : w.u[v * g.ndof + d0 + l]) - acc;
             const double fv = gv - xv;
             fmx = fmax(fmx, fabs(fv));
             gmx = fmax(gmx, fabs(gv));
@@ -712,7 +841,7 @@ __global__ void __launch_bounds__(256) k_and_dots(DevGrid g, DevWork w, const do
             w.gprev[base + e] = gv;
         }
     }
-    double *part = w.part + (int64_t(c) * tpc + tile) * kPartStride;
+    double *part = w.part + (int64_t(c) * part_tiles(g) + tile) * kPartStride;
     fmx = wave_max(fmx);
     gmx = wave_max(gmx);
     if (lane == 0) {
@@ -754,17 +883,16 @@ __global__ void __launch_bounds__(256) k_and_dots(DevGrid g, DevWork w, const do
     }
 }
 
-template <int N>
-__global__ void __launch_bounds__(64) k_and_solve(DevGrid g, DevWork w, int it, int max_iter, double tol,
-                                                  const int32_t *__restrict__ list, const int32_t *__restrict__ count,
-                                                  int tpc, int32_t *next, int32_t *next_count) {
-    if (int(blockIdx.x) >= *count) return;
-    const int c = list[blockIdx.x];
+// One wave: w.gamma[c][0..kuse) receives the coefficients, w.kuse[c] = kuse
+// and w.hist[2c + 1] the head slot of the history.
+__device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c, int32_t entry, int32_t *next,
+                                      int32_t *next_count) {
     const int lane = threadIdx.x;
     const int n = int(g.dof_ptr[c + 1] - g.dof_ptr[c]);
     const int ntile = (n + 63) / 64;
-    const double *part = w.part + int64_t(c) * tpc * kPartStride;
+    const double *part = w.part + int64_t(c) * part_tiles(g) * kPartStride;
     const int depth = w.depth;
+    const int it = w.iters[c];
     const bool hist_on = depth > 0 && it > 0;
     // reduce the per-tile partials in tile order
     double res = 0.0, gm = 0.0;
@@ -773,12 +901,12 @@ __global__ void __launch_bounds__(64) k_and_solve(DevGrid g, DevWork w, int it, 
         gm = fmax(gm, part[t * kPartStride + 1]);
     }
     const int it1 = it + 1;
-    const bool conv = res <= tol * fmax(1.0, gm);
-    const bool last = it1 >= max_iter;
+    const bool conv = res <= w.tol * fmax(1.0, gm);
+    const bool last = it1 >= w.max_iter;
     double *gam = w.gamma + int64_t(c) * kMaxDepth;
     if (lane == 0) {
         w.iters[c] = it1;
-        if (!(conv || last)) next[atomicAdd(next_count, 1)] = c;
+        if (!(conv || last)) next[atomicAdd(next_count, 1)] = entry;
         if (last && !conv) {
             atomicOr(&w.status[0], kStatusNoConv);
             atomicMin(&w.status[1], c);
@@ -883,29 +1011,62 @@ __global__ void __launch_bounds__(64) k_and_solve(DevGrid g, DevWork w, int it, 
 }
 
 template <int N>
-__global__ void __launch_bounds__(256) k_and_update(DevGrid g, DevWork w, const int32_t *__restrict__ list,
+__global__ void __launch_bounds__(256) k_round_dots(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
                                                     const int32_t *__restrict__ count, int tpc) {
+    __shared__ double accs[kPartStride][4];
+    const int n_items = *count * tpc;
+    for (int item = xcd_block(); item < n_items; item += gridDim.x) {
+        int slot, c;
+        decode(list[item / tpc], slot, c);
+        const DevGrid &g = tab[slot].g;
+        const DevWork &w = tab[slot].w;
+        const int tile = item % tpc;
+        if (tile * 64 >= int(g.dof_ptr[c + 1] - g.dof_ptr[c])) continue;
+        and_dots_tile<N>(g, w, c, tile, accs);
+        __syncthreads();  // accs is rewritten by the next item
+    }
+}
+
+__global__ void __launch_bounds__(64) k_round_solve(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
+                                                    const int32_t *__restrict__ count, int32_t *next,
+                                                    int32_t *next_count) {
+    const int n_items = *count;
+    for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int32_t entry = list[item];
+        int slot, c;
+        decode(entry, slot, c);
+        and_solve_cell(tab[slot].g, tab[slot].w, c, entry, next, next_count);
+    }
+}
+
+template <int N>
+__global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
+                                                      const int32_t *__restrict__ count, int tpc) {
     constexpr int nc = Dim<N>::nc;
-    const int lb = xcd_block();
-    if (lb / tpc >= *count) return;
-    const int c = list[lb / tpc];
-    const int tile = lb % tpc;
-    const int64_t d0 = g.dof_ptr[c];
-    const int n = int(g.dof_ptr[c + 1] - d0);
-    if (tile * 64 >= n) return;
-    const int64_t len = int64_t(n) * nc;
-    const int64_t base = d0 * nc;
-    const int kuse = w.kuse[c];
-    const int depth = w.depth;
-    const int head = w.hist[2 * c + 1];
-    const double *gam = w.gamma + int64_t(c) * kMaxDepth;
-    const double *dG = w.dG + base * (depth > 0 ? depth : 1);
-    const int64_t e0 = int64_t(tile) * 64 * nc;
-    const int64_t e1 = min(len, e0 + int64_t(64) * nc);
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        double xv = w.gprev[base + e];
-        for (int j = 0; j < kuse; ++j) xv -= gam[j] * dG[int64_t((head + j) % depth) * len + e];
-        w.x[base + e] = xv;
+    const int n_items = *count * tpc;
+    for (int item = xcd_block(); item < n_items; item += gridDim.x) {
+        int slot, c;
+        decode(list[item / tpc], slot, c);
+        const DevGrid &g = tab[slot].g;
+        const DevWork &w = tab[slot].w;
+        const int tile = item % tpc;
+        const int64_t d0 = g.dof_ptr[c];
+        const int n = int(g.dof_ptr[c + 1] - d0);
+        if (tile * 64 >= n) continue;
+        const int64_t len = int64_t(n) * nc;
+        const int64_t base = d0 * nc;
+        const int kuse = w.kuse[c];
+        const int depth = w.depth;
+        const int head = w.hist[2 * c + 1];
+        const double *gam = w.gamma + int64_t(c) * kMaxDepth;
+        const double *dG = w.dG + base * (depth > 0 ? depth : 1);
+        const int64_t e0 = int64_t(tile) * 64 * nc;
+        const int64_t e1 = min(len, e0 + int64_t(64) * nc);
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            double xv = w.gprev[base + e];
+            for (int j = 0; j < kuse; ++j) xv -= gam[j] * dG[int64_t((head + j) % depth) * len + e];
+            w.x[base + e] = xv;
+        }
     }
 }
 
@@ -916,8 +1077,9 @@ __global__ void __launch_bounds__(256) k_and_update(DevGrid g, DevWork w, const 
 // 2 A_k sum_j Z^[j'][j] G_j.  One value of the dissipation coefficient per
 // sub-triangle: the maximum over its nodes and both sides.
 template <int N>
-__global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w, double dt) {
+__global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w) {
     constexpr int nf = Dim<N>::nf;
+    const double dt = *w.dt;
     constexpr int tpb = 256 / nf;
     __shared__ double lam_s[tpb][nf], lamv_s[tpb][nf];
     __shared__ double G_s[tpb][nf][5];
@@ -1005,6 +1167,47 @@ __global__ void k_reset_status(DevWork w, int n_cells) {
         w.status[1] = INT_MAX;
         w.status[2] = n_cells;
         w.status[3] = 0;
+        w.status[4] = 0;
+        w.status[5] = 0;
+        w.status[6] = 0;
+        w.status[7] = 0;
+    }
+}
+
+// Predictor iteration counts over the cells of one simulation: status[4] =
+// min, status[5] = max, status[6..7] = 64-bit sum.
+__global__ void __launch_bounds__(1024) k_step_stats(DevWork w, int n_cells) {
+    __shared__ int smin[16], smax[16];
+    __shared__ unsigned long long ssum[16];
+    int mn = INT_MAX, mx = 0;
+    unsigned long long sum = 0;
+    for (int i = threadIdx.x; i < n_cells; i += blockDim.x) {
+        const int v = w.iters[i];
+        mn = min(mn, v);
+        mx = max(mx, v);
+        sum += unsigned(v);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        mn = min(mn, __shfl_xor(mn, o, kWave));
+        mx = max(mx, __shfl_xor(mx, o, kWave));
+        sum += __shfl_xor(sum, o, kWave);
+    }
+    const int wv = threadIdx.x / kWave;
+    if (threadIdx.x % kWave == 0) {
+        smin[wv] = mn;
+        smax[wv] = mx;
+        ssum[wv] = sum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < int(blockDim.x) / kWave; ++i) {
+            mn = min(mn, smin[i]);
+            mx = max(mx, smax[i]);
+            sum += ssum[i];
+        }
+        w.status[4] = n_cells > 0 ? mn : 0;
+        w.status[5] = mx;
+        *reinterpret_cast<unsigned long long *>(w.status + 6) = sum;
     }
 }
 
@@ -1073,72 +1276,111 @@ hipError_t launch_detect(const DevGrid &g, const DevWork &w, const double *u, hi
     });
 }
 
-hipError_t launch_cfl_max(const DevGrid &g, const DevWork &w, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_cfl_max, dim3(1), dim3(1024), 0, s, g.n_cells, w.cflterm, out);
+hipError_t launch_cfl_dt(const DevGrid &g, const DevWork &w, double cfl, double h_min, double *smax, hipStream_t s) {
+    hipLaunchKernelGGL(k_cfl_dt, dim3(1), dim3(1024), 0, s, g.n_cells, w, smax, cfl, h_min, 2 * g.N + 1);
     return hipGetLastError();
 }
 
-hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, const double *u, hipStream_t s) {
+hipError_t launch_set_dt(const DevWork &w, double dt, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_double, dim3(1), dim3(64), 0, s, w.dt, dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, int slot, int32_t *list, int64_t base, hipStream_t s) {
     return dispatch(g.N, [&](auto n) {
         int64_t m = g.ndof > g.n_cells ? g.ndof : g.n_cells;
-        hipLaunchKernelGGL(k_pred_init<decltype(n)::value>, dim3(blocks_for(m, 256)), dim3(256), 0, s, g, w, u);
+        hipLaunchKernelGGL(k_pred_init<decltype(n)::value>, dim3(blocks_for(m, 256)), dim3(256), 0, s, g, w, slot,
+                           list, base);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_pred_iteration(const DevGrid &g, const DevWork &w, const double *u, double dt, int it,
-                                 int max_iter, double tol, const int32_t *list, const int32_t *count, int n_upper,
-                                 int32_t *next, int32_t *next_count, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1,
-                                 unsigned long long *bytes) {
-    return dispatch(g.N, [&](auto n) {
+hipError_t launch_set_count(int32_t *count, int value, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
+    return dispatch(a.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        const unsigned nl = unsigned(n_upper);
-        const int chunks = (g.max_cell_subtets + D::spb - 1) / D::spb;
-        hipLaunchKernelGGL((k_subtet<NN, false>), dim3(nl * chunks), dim3(D::threads), 0, s, g, w, dt, list, count,
-                           chunks, u);
-        const int per = int((int64_t(g.max_cell_dofs) * D::nc + 255) / 256);
-        hipLaunchKernelGGL(k_gather<NN>, dim3(nl * per), dim3(256), 0, s, g, w, list, count, per);
-        const int tpc = (g.max_cell_dofs + 63) / 64;
-        if (ev0) (void)hipEventRecord(ev0, s);
-        if (g.mixed)
-            hipLaunchKernelGGL((k_minv_f32<D::nc>), dim3(nl * tpc), dim3(256), 0, s, g, list, count, w.R32, w.S, tpc,
-                               bytes);
+        const int chunks = (a.max_cell_subtets + D::spb - 1) / D::spb;
+        const int tpc = (a.max_cell_dofs + 63) / 64;
+        // persistent grid, or one workgroup per item of the longest possible list
+        auto grid = [&](int persistent, int per) {
+            return dim3(persistent > 0 ? unsigned(persistent) : unsigned(std::max(1, a.n_upper * per)));
+        };
+        const int per = int((int64_t(a.max_cell_dofs) * D::nc + 255) / 256);
+        hipLaunchKernelGGL(k_round_subtet<NN>, grid(a.shape.g_sub, chunks), dim3(D::threads), 0, s, a.tab, a.list,
+                           a.count, chunks, a.next_count);
+        hipLaunchKernelGGL(k_round_gather<NN>, grid(a.shape.g_gather, per), dim3(256), 0, s, a.tab, a.list, a.count,
+                           per);
+        if (a.ev0) (void)hipEventRecord(a.ev0, s);
+        if (a.mixed)
+            hipLaunchKernelGGL(k_round_minv32<D::nc>, grid(a.shape.g_minv, tpc), dim3(256), 0, s, a.tab, a.list,
+                               a.count, tpc, a.bytes);
         else
-            hipLaunchKernelGGL((k_minv<D::nc, 0>), dim3(nl * tpc), dim3(256), 0, s, g, list, count, w.R, w.S, tpc,
-                               bytes);
-        if (ev1) (void)hipEventRecord(ev1, s);
-        hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, next_count);
-        hipLaunchKernelGGL(k_and_dots<NN>, dim3(nl * tpc), dim3(256), 0, s, g, w, u, it, list, count, tpc);
-        hipLaunchKernelGGL(k_and_solve<NN>, dim3(nl), dim3(64), 0, s, g, w, it, max_iter, tol, list, count, tpc, next,
-                           next_count);
-        hipLaunchKernelGGL(k_and_update<NN>, dim3(nl * tpc), dim3(256), 0, s, g, w, list, count, tpc);
+            hipLaunchKernelGGL(k_round_minv<D::nc>, grid(a.shape.g_minv, tpc), dim3(256), 0, s, a.tab, a.list, a.count,
+                               tpc, a.bytes);
+        if (a.ev1) (void)hipEventRecord(a.ev1, s);
+        hipLaunchKernelGGL(k_round_dots<NN>, grid(a.shape.g_dots, tpc), dim3(256), 0, s, a.tab, a.list, a.count, tpc);
+        hipLaunchKernelGGL(k_round_solve, grid(a.shape.g_solve, 1), dim3(kWave), 0, s, a.tab, a.list, a.count, a.next,
+                           a.next_count);
+        hipLaunchKernelGGL(k_round_update<NN>, grid(a.shape.g_update, tpc), dim3(256), 0, s, a.tab, a.list, a.count,
+                           tpc);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, double dt, hipStream_t s) {
+hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, hipStream_t s) {
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        hipLaunchKernelGGL((k_subtet<NN, true>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w, dt,
-                           nullptr, nullptr, 1, nullptr);
+        hipLaunchKernelGGL(k_subtet_post<NN>, dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, double dt, hipStream_t s) {
+hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, hipStream_t s) {
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        hipLaunchKernelGGL(k_face<NN>, dim3(blocks_for(g.nsub, 256 / D::nf)), dim3(256), 0, s, g, w, dt);
+        hipLaunchKernelGGL(k_face<NN>, dim3(blocks_for(g.nsub, 256 / D::nf)), dim3(256), 0, s, g, w);
         hipLaunchKernelGGL(k_rhs<NN>, dim3(blocks_for(g.ndof * 5, 256)), dim3(256), 0, s, g, w);
         const int tpc = (g.max_cell_dofs + 63) / 64;
-        hipLaunchKernelGGL((k_minv<5, 1>), dim3(unsigned(g.n_cells) * tpc), dim3(256), 0, s, g, nullptr, nullptr,
-                           w.rhs, u, tpc, nullptr);
+        hipLaunchKernelGGL(k_minv_update<5>, dim3(unsigned(g.n_cells) * tpc), dim3(256), 0, s, g, w.rhs, u, tpc);
         hipLaunchKernelGGL(k_positivity, dim3(blocks_for(g.ndof, 256)), dim3(256), 0, s, g, w, u);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_step_stats(const DevGrid &g, const DevWork &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(1024), 0, s, w, g.n_cells);
+    return hipGetLastError();
+}
+
+IterShape resident_shape(int N, int mixed) {
+    IterShape sh;
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    auto fit = [&](const void *f, int threads) {
+        int per = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, threads, 0) != hipSuccess || per < 1) per = 1;
+        return per * cus;
+    };
+    (void)dispatch(N, [&](auto n) {
+        constexpr int NN = decltype(n)::value;
+        using D = Dim<NN>;
+        sh.g_sub = fit(reinterpret_cast<const void *>(&k_round_subtet<NN>), D::threads);
+        sh.g_gather = fit(reinterpret_cast<const void *>(&k_round_gather<NN>), 256);
+        sh.g_minv = mixed ? fit(reinterpret_cast<const void *>(&k_round_minv32<D::nc>), 256)
+                          : fit(reinterpret_cast<const void *>(&k_round_minv<D::nc>), 256);
+        sh.g_dots = fit(reinterpret_cast<const void *>(&k_round_dots<NN>), 256);
+        sh.g_solve = fit(reinterpret_cast<const void *>(&k_round_solve), kWave);
+        sh.g_update = fit(reinterpret_cast<const void *>(&k_round_update<NN>), 256);
+        return hipSuccess;
+    });
+    return sh;
 }
 
 }  // namespace afe
