@@ -13,6 +13,7 @@ u = (1,1,1), p = 1 on the periodic Voronoi mesh of 16^3 jittered-lattice seeds
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -173,6 +174,42 @@ def cpu_baseline(mesh, N, u0_np, dt, budget_s: float = 20.0, cluster_size: int =
     }
 
 
+SERVE = dict(count=32, rate=10.0, seed=3, n_range=(4, 10), degrees=(2, 3), steps=10, cfl=0.004,
+             reserve_gib=16,
+             desc=("inviscid Taylor-Green vortex requests on [0, 2 pi)^3 (Mach 0.1, mixed precision), "
+                   "periodic Voronoi of n^3 jittered seeds, n ~ U{4..10}, N ~ U{2, 3}, 10 steps each, "
+                   "Poisson arrivals 10/s, 32 requests (seed 3)"))
+
+
+def serving_run(log) -> dict:
+    """Continuous-batching session over the request stream; p50/p99 latency
+    and aggregate DOF-updates/s."""
+    import torch
+
+    from afe_inputs.fields import taylor_green_3d
+    from afe_inputs.requests import taylor_green_requests
+    from paper_2605_00619_amd import afe
+    from paper_2605_00619_amd.serve import GpuBackend, Request, Server, summarize
+
+    t0 = time.time()
+    raw = taylor_green_requests(SERVE["count"], SERVE["rate"], SERVE["seed"], SERVE["n_range"], SERVE["degrees"],
+                                SERVE["steps"])
+    log(f"serving: {len(raw)} request meshes in {time.time() - t0:.1f}s")
+    params = afe.Params(mu=0.0, precision=afe.AFE_MIXED, max_iter=400)
+    reqs = [Request(d["rid"], d["arrival"], d["mesh"], d["N"], d["steps"], SERVE["cfl"], taylor_green_3d, params)
+            for d in raw]
+    free, _ = torch.cuda.mem_get_info()
+    budget = free - SERVE["reserve_gib"] * 2**30
+    srv = Server(GpuBackend(), budget)
+    res = srv.run(reqs)
+    out = summarize(res)
+    out.update(workload=SERVE["desc"], hbm_budget_bytes=int(budget), peak_admitted_bytes=int(srv.peak_bytes),
+               batch_steps=srv.steps_run, total_dofs=int(sum(r.ndof for r in res)),
+               statuses=sorted({r.status for r in res}))
+    log(f"serving: {out}")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +222,9 @@ def main() -> int:
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--precision", choices=("fp64", "mixed"), default="fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving session")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving session")
+    ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner's")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -192,6 +232,11 @@ def main() -> int:
     args = ap.parse_args()
     if args.summarize_counters:
         return summarize_counters(*args.summarize_counters)
+    if args.serve_only:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(serving_run(log)), flush=True)
+        return 0
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
               "(the method is cell-local, a multi-GPU run would shard cells; not built)", file=sys.stderr)
@@ -232,27 +277,32 @@ def main() -> int:
         log(f"copy probe: {n * 8} bytes read, {n * 8} bytes written")
         del src, dst
 
-    def one_step():
-        dt = cd.cfl_dt(u, args.cfl)
-        rep = cd.step(u, dt)
-        return dt, rep
-
+    batch = afe.Batch()
+    batch.attach(cd, u, args.cfl)
+    t0 = time.time()
+    shape = batch.tune() if not args.no_tune else batch.shape
+    log(f"launch shape {shape} ({'tuned' if not args.no_tune else 'default'}) in {time.time() - t0:.1f}s")
+    if shape.graph:
+        # the timed steps carry HIP events around the M^-1 launches, which graph replay would not
+        shape = dataclasses.replace(shape, graph=False)
+        batch.shape = shape
     for i in range(args.warmup):
-        dt, rep = one_step()
-        log(f"warmup {i}: dt={dt:.3e} iters {rep.iters_min}/{rep.iters_mean:.1f}/{rep.iters_max}")
+        rep = batch.step()[0]
+        log(f"warmup {i}: dt={rep.dt:.3e} iters {rep.iters_min}/{rep.iters_mean:.1f}/{rep.iters_max}")
     torch.cuda.synchronize()
-    cd.profile_enable(True)
+    batch.profile_enable(True)
     iters = []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
-        dt, rep = one_step()
+        rep = batch.step()[0]
         iters.append(rep.iters_mean)
-        log(f"step {i}: dt={dt:.3e} iters {rep.iters_min}/{rep.iters_mean:.1f}/{rep.iters_max}")
+        log(f"step {i}: dt={rep.dt:.3e} iters {rep.iters_min}/{rep.iters_mean:.1f}/{rep.iters_max}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    k_ms, k_launches, k_bytes = cd.profile_read()
-    cd.profile_enable(False)
+    dt = rep.dt
+    k_ms, k_launches, k_bytes = batch.profile_read()
+    batch.profile_enable(False)
     ms_per_step = 1e3 * elapsed / args.steps
     value = cd.ndof * 5 * args.steps / elapsed
     achieved = (k_bytes / k_launches) / (k_ms / k_launches * 1e-3) / 1e9 if k_launches else None
@@ -267,6 +317,8 @@ def main() -> int:
             "workload": wl["desc"], "name": args.workload, "cells": cd.n_cells, "ndof": cd.ndof, "subtets": cd.n_subtets,
             "N": wl["N"], "cfl": args.cfl, "dt_last": dt, "predictor_iters_mean": float(np.mean(iters)),
             "anderson_depth": args.depth, "tol": args.tol,
+            "launch_shape": {"sub": shape.sub, "minv": shape.minv, "anderson": shape.anderson,
+                             "rounds": shape.rounds, "graph": bool(shape.graph)},
         },
         "copy_probe_bytes": copy_bytes,
         "roofline": {
@@ -281,6 +333,8 @@ def main() -> int:
             "share_of_step_time": (k_ms / 1e3) / elapsed,
         },
     }
+    if not args.no_serve:
+        out["serving"] = serving_run(log)
     if not args.no_cpu_baseline:
         t0 = time.time()
         out["cpu_baseline"] = cpu_baseline(mesh, wl["N"], u0.cpu().numpy(), dt)

@@ -114,54 +114,130 @@ __global__ void __launch_bounds__(256) k_mass_assemble(DevGrid g) {
     }
 }
 
-// In-place inverse of M_i: Jacobi scaling to unit diagonal, Gauss-Jordan
-// elimination without pivoting (the scaled matrix is symmetric positive
-// definite), unscaling, symmetrisation.
-__global__ void __launch_bounds__(1024) k_mass_invert(DevGrid g) {
-    extern __shared__ double sh[];
+// In-place inverse of M_i: Jacobi scaling to unit diagonal, blocked
+// Gauss-Jordan elimination without pivoting (the scaled matrix is symmetric
+// positive definite), unscaling, symmetrisation.  Pivots are taken kPanel at
+// a time: with K the panel's rows/columns and O the others, one panel step is
+//   A_KK <- A_KK^{-1},  A_KO <- A_KK^{-1} A_KO,
+//   A_OK <- -A_OK A_KK^{-1},  A_OO <- A_OO - A_OK A_KK^{-1} A_KO,
+// which equals kPanel single-pivot Gauss-Jordan steps.  The pivot block is
+// inverted in LDS; each thread owns matrix columns, holds the column's new
+// panel entries in registers and applies the rank-kPanel update to the other
+// rows, whose panel entries are staged through LDS 64 rows at a time.
+constexpr int kPanel = 32;
+constexpr int kRowChunk = 64;
+constexpr int kInvThreads = 512;
+
+__global__ void __launch_bounds__(kInvThreads) k_mass_invert(DevGrid g) {
+    __shared__ double P[kPanel][kPanel + 1];
+    __shared__ double Rs[kRowChunk][kPanel];
+    extern __shared__ double dsc[];
     const int c = blockIdx.x;
     const int n = int(g.dof_ptr[c + 1] - g.dof_ptr[c]);
     double *A = g.minv + g.minv_ptr[c];
     const int64_t ld = minv_ld(n);
-    double *dsc = sh;
-    double *rowk = sh + n;
-    double *colk = sh + 2 * n;
     const int tid = threadIdx.x, nth = blockDim.x;
-    const int tx = tid % 64, ty = tid / 64, ny = nth / 64;
     for (int i = tid; i < n; i += nth) {
         dsc[i] = 1.0 / sqrt(A[int64_t(i) * ld + i]);
         g.dscale[g.dof_ptr[c] + i] = dsc[i];
     }
     __syncthreads();
-    for (int i = ty; i < n; i += ny)
-        for (int j = tx; j < n; j += 64) A[int64_t(i) * ld + j] *= dsc[i] * dsc[j];
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double piv = A[int64_t(k) * ld + k];
-        const double ip = 1.0 / piv;
-        for (int j = tid; j < n; j += nth) {
-            rowk[j] = (j == k ? 1.0 : A[int64_t(k) * ld + j]) * ip;
-            colk[j] = (j == k ? 0.0 : A[int64_t(j) * ld + k]);
-        }
-        __syncthreads();
-        for (int i = ty; i < n; i += ny) {
-            const double ci = colk[i];
-            double *Ai = A + int64_t(i) * ld;
-            if (i == k) {
-                for (int j = tx; j < n; j += 64) Ai[j] = rowk[j];
-            } else {
-                for (int j = tx; j < n; j += 64) Ai[j] = (j == k ? 0.0 : Ai[j]) - ci * rowk[j];
-            }
-        }
-        __syncthreads();
+    for (int64_t e = tid; e < int64_t(n) * n; e += nth) {
+        const int i = int(e / n), j = int(e % n);
+        A[int64_t(i) * ld + j] *= dsc[i] * dsc[j];
     }
-    for (int i = ty; i < n; i += ny)
-        for (int j = tx; j < n; j += 64) {
-            if (j < i) continue;
-            const double v = 0.5 * (A[int64_t(i) * ld + j] + A[int64_t(j) * ld + i]) * dsc[i] * dsc[j];
-            A[int64_t(i) * ld + j] = v;
-            A[int64_t(j) * ld + i] = v;
+    __syncthreads();
+    for (int k0 = 0; k0 < n; k0 += kPanel) {
+        const int b = min(kPanel, n - k0);
+        // pivot block inverse (single-pivot Gauss-Jordan in LDS); thread tid
+        // owns entries tid + q * nth of the kPanel x kPanel block
+        constexpr int kPer = (kPanel * kPanel + kInvThreads - 1) / kInvThreads;
+        for (int q = 0; q < kPer; ++q) {
+            const int t = tid + q * nth, pi = t / kPanel, pj = t % kPanel;
+            if (t < kPanel * kPanel && pi < b && pj < b) P[pi][pj] = A[int64_t(k0 + pi) * ld + k0 + pj];
         }
+        __syncthreads();
+        for (int p = 0; p < b; ++p) {
+            const double ip = 1.0 / P[p][p];
+            double nv[kPer];
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int t = tid + q * nth, pi = t / kPanel, pj = t % kPanel;
+                nv[q] = 0.0;
+                if (t < kPanel * kPanel && pi < b && pj < b) {
+                    const double rowp = (pj == p ? 1.0 : P[p][pj]) * ip;
+                    nv[q] = pi == p ? rowp : (pj == p ? 0.0 : P[pi][pj]) - P[pi][p] * rowp;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int t = tid + q * nth, pi = t / kPanel, pj = t % kPanel;
+                if (t < kPanel * kPanel && pi < b && pj < b) P[pi][pj] = nv[q];
+            }
+            __syncthreads();
+        }
+        // columns owned by this thread: new panel entries T[:, j].  With more
+        // columns than threads, the group holding the panel columns goes last:
+        // the other groups' updates read the panel columns' old entries.
+        const int ngroups = (n + nth - 1) / nth, gK = k0 / nth;
+        for (int q = 0; q < ngroups; ++q) {
+            const int j0 = ((gK + 1 + q) % ngroups) * nth;
+            const int j = j0 + tid;
+            const bool own = j < n;
+            const bool inK = j >= k0 && j < k0 + b;
+            double T[kPanel];
+#pragma unroll
+            for (int k = 0; k < kPanel; ++k) T[k] = 0.0;
+            if (own) {
+                if (inK) {
+#pragma unroll
+                    for (int k = 0; k < kPanel; ++k) T[k] = k < b ? P[k][j - k0] : 0.0;
+                } else {
+                    for (int m = 0; m < b; ++m) {
+                        const double am = A[int64_t(k0 + m) * ld + j];
+#pragma unroll
+                        for (int k = 0; k < kPanel; ++k) T[k] = fma(k < b ? P[k][m] : 0.0, am, T[k]);
+                    }
+                }
+            }
+            // rank-b update of the other rows, 64 rows at a time
+            for (int r0 = 0; r0 < n; r0 += kRowChunk) {
+                const int rn = min(kRowChunk, n - r0);
+                __syncthreads();
+                for (int t = tid; t < rn * kPanel; t += nth) {
+                    const int r = t / kPanel, k = t % kPanel;
+                    Rs[r][k] = k < b ? A[int64_t(r0 + r) * ld + k0 + k] : 0.0;
+                }
+                __syncthreads();
+                if (own) {
+                    for (int r = 0; r < rn; ++r) {
+                        const int i = r0 + r;
+                        if (i >= k0 && i < k0 + b) continue;
+                        double acc = inK ? 0.0 : A[int64_t(i) * ld + j];
+#pragma unroll
+                        for (int k = 0; k < kPanel; ++k) acc = fma(-Rs[r][k], T[k], acc);
+                        A[int64_t(i) * ld + j] = acc;
+                    }
+                }
+            }
+            __syncthreads();
+            // the panel rows take their new entries last (the update read their old ones)
+            if (own) {
+#pragma unroll
+                for (int k = 0; k < kPanel; ++k)
+                    if (k < b) A[int64_t(k0 + k) * ld + j] = T[k];
+            }
+            __syncthreads();
+        }
+    }
+    for (int64_t e = tid; e < int64_t(n) * n; e += nth) {
+        const int i = int(e / n), j = int(e % n);
+        if (j < i) continue;
+        const double v = 0.5 * (A[int64_t(i) * ld + j] + A[int64_t(j) * ld + i]) * dsc[i] * dsc[j];
+        A[int64_t(i) * ld + j] = v;
+        A[int64_t(j) * ld + i] = v;
+    }
 }
 
 // FP32 copy of the Jacobi-scaled inverse: M_i^{-1} = D A D with D = diag(M_i)^{-1/2};
@@ -1258,8 +1334,8 @@ hipError_t launch_mass_assemble(const DevGrid &g, hipStream_t s) {
 }
 
 hipError_t launch_mass_invert(const DevGrid &g, hipStream_t s) {
-    size_t shmem = size_t(3) * g.max_cell_dofs * sizeof(double);
-    hipLaunchKernelGGL(k_mass_invert, dim3(g.n_cells), dim3(1024), shmem, s, g);
+    size_t shmem = size_t(g.max_cell_dofs) * sizeof(double);
+    hipLaunchKernelGGL(k_mass_invert, dim3(g.n_cells), dim3(kInvThreads), shmem, s, g);
     if (g.mixed) hipLaunchKernelGGL(k_minv_to_f32, dim3(g.n_cells), dim3(256), 0, s, g);
     return hipGetLastError();
 }
