@@ -48,7 +48,7 @@ def kernel_source_hash() -> str:
 
 def dominant_kernel(precision: str, N: int) -> str:
     nc = 5 * (N + 1)
-    return f"k_minv<{nc}, 0>" if precision == "fp64" else f"k_minv_f32<{nc}>"
+    return f"k_round_minv<{nc}>" if precision == "fp64" else f"k_round_minv32<{nc}>"
 
 
 def traffic_path(workload: str, precision: str) -> str:
