@@ -26,10 +26,14 @@ sys.path.insert(0, ROOT)
 METRIC = "DOF-updates/s per ADER step, mixed vs FP64 at L2 err; p50/p99 solve latency"
 
 WORKLOADS = {
-    "wave16_p3": dict(n=16, jitter=0.25, seed=1, N=3,
+    "wave16_p3": dict(n=16, jitter=0.25, seed=1, N=3, merge=None,
                       desc="density wave, periodic Voronoi 16^3 seeds (+-0.25h, seed 1), N=3, FP64"),
-    "wave6_p2": dict(n=6, jitter=0.2, seed=0, N=2,
+    "wave6_p2": dict(n=6, jitter=0.2, seed=0, N=2, merge=None,
                      desc="density wave, periodic Voronoi 6^3 seeds (+-0.2h, seed 0), N=2, FP64"),
+    # the same seeds with Voronoi edges shorter than 2% of the seed spacing collapsed
+    "wave16_p3_q": dict(n=16, jitter=0.25, seed=1, N=3, merge=0.02,
+                        desc="density wave, periodic Voronoi 16^3 seeds (+-0.25h, seed 1), edges < 2% of "
+                             "the seed spacing collapsed, N=3, FP64"),
 }
 HBM_PEAK_GBS = 8000.0
 
@@ -210,6 +214,93 @@ def serving_run(log) -> dict:
     return out
 
 
+def run_workload(args, key: str, precision: str, log, start=None, keep_initial: bool = False) -> dict:
+    """Build the workload, autotune the launch shape, run the warm-up and the
+    timed steps with the M^-1 kernel's HIP events and byte counter."""
+    import numpy as np
+    import torch
+
+    from afe_inputs.fields import density_wave
+    from afe_inputs.mesh import jittered_lattice_seeds, periodic_voronoi
+    from paper_2605_00619_amd import afe
+
+    wl = WORKLOADS[key]
+    t0 = time.time()
+    mesh = periodic_voronoi(jittered_lattice_seeds(wl["n"], wl["jitter"], wl["seed"]),
+                            merge_tol=None if wl["merge"] is None else wl["merge"] / wl["n"])
+    log(f"[{key} {precision}] mesh: {mesh['n_cells']} cells in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    params = afe.Params(accel_depth=args.depth, max_iter=args.max_iter, tol=args.tol,
+                        precision=afe.AFE_MIXED if precision == "mixed" else afe.AFE_FP64)
+    cd = afe.CellData(mesh, wl["N"], params)
+    torch.cuda.synchronize()
+    log(f"[{key} {precision}] cell data: ndof={cd.ndof} subtets={cd.n_subtets} max_cell_dofs={cd.max_cell_dofs} "
+        f"device={cd.device_bytes / 2**30:.2f} GiB in {time.time() - t0:.1f}s")
+    if start is None:
+        x = cd.dof_coords()
+        prim = torch.tensor(density_wave(np.mod(x.cpu().numpy().T, 1.0)).T.copy(), device="cuda")
+        u = cd.prim_to_cons(prim)
+        del x, prim
+    else:
+        u = start.clone()
+    u_start = u.clone()
+    batch = afe.Batch()
+    batch.attach(cd, u, args.cfl)
+    t0 = time.time()
+    shape = batch.tune() if not args.no_tune else batch.shape
+    log(f"[{key} {precision}] launch shape {shape} ({'tuned' if not args.no_tune else 'default'}) "
+        f"in {time.time() - t0:.1f}s")
+    if shape.graph:
+        # the timed steps carry HIP events around the M^-1 launches, which graph replay would not
+        shape = dataclasses.replace(shape, graph=False)
+        batch.shape = shape
+    for i in range(args.warmup):
+        rep = batch.step()[0]
+        log(f"[{key} {precision}] warmup {i}: dt={rep.dt:.3e} iters {rep.iters_min}/{rep.iters_mean:.1f}/{rep.iters_max}")
+    torch.cuda.synchronize()
+    batch.profile_enable(True)
+    iters, iters_max = [], 0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        rep = batch.step()[0]
+        iters.append(rep.iters_mean)
+        iters_max = max(iters_max, rep.iters_max)
+        log(f"[{key} {precision}] step {i}: dt={rep.dt:.3e} iters {rep.iters_min}/{rep.iters_mean:.1f}/{rep.iters_max}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    k_ms, k_launches, k_bytes = batch.profile_read()
+    batch.profile_enable(False)
+    achieved = (k_bytes / k_launches) / (k_ms / k_launches * 1e-3) / 1e9 if k_launches else None
+    res = {
+        "value": cd.ndof * 5 * args.steps / elapsed, "ms_per_step": 1e3 * elapsed / args.steps,
+        "iters_mean": float(np.mean(iters)), "iters_max": int(iters_max), "dt": rep.dt,
+        "cells": cd.n_cells, "ndof": cd.ndof, "subtets": cd.n_subtets, "mesh": mesh,
+        "shape": {"sub": shape.sub, "minv": shape.minv, "anderson": shape.anderson, "rounds": shape.rounds,
+                  "graph": bool(shape.graph)},
+        "roofline": {
+            "kernel": dominant_kernel(precision, wl["N"]) + (
+                " (FP64 M_i^-1 applied to the predictor's space-time blocks)" if precision == "fp64" else
+                " (FP32 scaled M_i^-1 applied to the predictor's residual blocks)"),
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
+            "traffic": measured_traffic(key, precision, k_bytes / max(k_launches, 1)),
+            "avg_launch_ms": k_ms / max(k_launches, 1), "launches": k_launches,
+            "algorithmic_bytes_per_launch": k_bytes / max(k_launches, 1),
+            "algorithmic_bytes_basis": "M_i^-1 as stored (8 n_i^2) + right-hand side read and result written "
+                                       "(16 n_i 5(N+1)) per cell and iteration",
+            "share_of_step_time": (k_ms / 1e3) / elapsed,
+        },
+        "u_end": u.clone(), "u_start": u_start if start is None else None,
+        "u_initial": u_start if keep_initial else None,
+    }
+    batch.close()
+    cd.close()
+    del u
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +316,8 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving session")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving session")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner's")
+    ap.add_argument("--no-legs", dest="legs", action="store_false",
+                    help="skip the mixed-precision and mesh-variant legs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -251,21 +344,6 @@ def main() -> int:
 
     wl = WORKLOADS[args.workload]
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
-    t0 = time.time()
-    mesh = periodic_voronoi(jittered_lattice_seeds(wl["n"], wl["jitter"], wl["seed"]))
-    log(f"mesh: {mesh['n_cells']} cells in {time.time() - t0:.1f}s")
-    t0 = time.time()
-    params = afe.Params(accel_depth=args.depth, max_iter=args.max_iter, tol=args.tol,
-                        precision=afe.AFE_MIXED if args.precision == "mixed" else afe.AFE_FP64)
-    cd = afe.CellData(mesh, wl["N"], params)
-    torch.cuda.synchronize()
-    log(f"cell data: ndof={cd.ndof} subtets={cd.n_subtets} max_cell_dofs={cd.max_cell_dofs} "
-        f"device={cd.device_bytes / 2**30:.2f} GiB in {time.time() - t0:.1f}s")
-    x = cd.dof_coords()
-    prim = torch.tensor(density_wave(np.mod(x.cpu().numpy().T, 1.0)).T.copy(), device="cuda")
-    u = cd.prim_to_cons(prim)
-    u0 = u.clone()
     copy_bytes = 0
     if args.copy_probe_mib:
         n = args.copy_probe_mib * 2**20 // 8
@@ -277,67 +355,44 @@ def main() -> int:
         log(f"copy probe: {n * 8} bytes read, {n * 8} bytes written")
         del src, dst
 
-    batch = afe.Batch()
-    batch.attach(cd, u, args.cfl)
-    t0 = time.time()
-    shape = batch.tune() if not args.no_tune else batch.shape
-    log(f"launch shape {shape} ({'tuned' if not args.no_tune else 'default'}) in {time.time() - t0:.1f}s")
-    if shape.graph:
-        # the timed steps carry HIP events around the M^-1 launches, which graph replay would not
-        shape = dataclasses.replace(shape, graph=False)
-        batch.shape = shape
-    for i in range(args.warmup):
-        rep = batch.step()[0]
-        log(f"warmup {i}: dt={rep.dt:.3e} iters {rep.iters_min}/{rep.iters_mean:.1f}/{rep.iters_max}")
-    torch.cuda.synchronize()
-    batch.profile_enable(True)
-    iters = []
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        rep = batch.step()[0]
-        iters.append(rep.iters_mean)
-        log(f"step {i}: dt={rep.dt:.3e} iters {rep.iters_min}/{rep.iters_mean:.1f}/{rep.iters_max}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    dt = rep.dt
-    k_ms, k_launches, k_bytes = batch.profile_read()
-    batch.profile_enable(False)
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = cd.ndof * 5 * args.steps / elapsed
-    achieved = (k_bytes / k_launches) / (k_ms / k_launches * 1e-3) / 1e9 if k_launches else None
-    traffic = measured_traffic(args.workload, args.precision, k_bytes / max(k_launches, 1))
+    main_run = run_workload(args, args.workload, args.precision, log, keep_initial=not args.no_cpu_baseline)
+    r = main_run
     out = {
-        "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "metric": METRIC, "value": r["value"], "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f64 (predictor preconditioner f32)",
         "data": "synthetic",
         "config": {
-            "workload": wl["desc"], "name": args.workload, "cells": cd.n_cells, "ndof": cd.ndof, "subtets": cd.n_subtets,
-            "N": wl["N"], "cfl": args.cfl, "dt_last": dt, "predictor_iters_mean": float(np.mean(iters)),
-            "anderson_depth": args.depth, "tol": args.tol,
-            "launch_shape": {"sub": shape.sub, "minv": shape.minv, "anderson": shape.anderson,
-                             "rounds": shape.rounds, "graph": bool(shape.graph)},
+            "workload": wl["desc"], "name": args.workload, "cells": r["cells"], "ndof": r["ndof"],
+            "subtets": r["subtets"], "N": wl["N"], "cfl": args.cfl, "dt_last": r["dt"],
+            "predictor_iters_mean": r["iters_mean"], "predictor_iters_max": r["iters_max"],
+            "anderson_depth": args.depth, "tol": args.tol, "launch_shape": r["shape"],
         },
         "copy_probe_bytes": copy_bytes,
-        "roofline": {
-            "kernel": dominant_kernel(args.precision, wl["N"]) + (
-                " (FP64 M_i^-1 applied to the predictor's space-time blocks)" if args.precision == "fp64" else
-                " (FP32 scaled M_i^-1 applied to the predictor's residual blocks)"),
-            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": traffic,
-            "avg_launch_ms": k_ms / max(k_launches, 1), "launches": k_launches,
-            "algorithmic_bytes_per_launch": k_bytes / max(k_launches, 1),
-            "share_of_step_time": (k_ms / 1e3) / elapsed,
-        },
+        "roofline": r["roofline"],
     }
+    if args.legs and args.precision == "fp64":
+        # the same workload in mixed precision from the same initial state and the
+        # same number of steps: throughput and distance of the final states
+        mixed = run_workload(args, args.workload, "mixed", log, start=main_run["u_start"])
+        diff = float((mixed["u_end"] - main_run["u_end"]).abs().max() / main_run["u_end"].abs().max())
+        out["mixed"] = {k: mixed[k] for k in ("value", "ms_per_step", "iters_mean", "iters_max")}
+        out["mixed"]["roofline"] = mixed["roofline"]
+        out["mixed"]["rel_linf_vs_fp64_final_state"] = diff
+        del mixed
+        q = run_workload(args, "wave16_p3_q" if args.workload == "wave16_p3" else args.workload, "fp64", log)
+        out["mesh_variant"] = {k: q[k] for k in ("value", "ms_per_step", "iters_mean", "iters_max", "ndof")}
+        out["mesh_variant"]["workload"] = WORKLOADS["wave16_p3_q"]["desc"] if args.workload == "wave16_p3" else ""
+        del q
+    u0_np = main_run["u_initial"].cpu().numpy() if main_run.get("u_initial") is not None else None
+    mesh, dt = main_run["mesh"], main_run["dt"]
+    del main_run, r
     if not args.no_serve:
         out["serving"] = serving_run(log)
     if not args.no_cpu_baseline:
         t0 = time.time()
-        out["cpu_baseline"] = cpu_baseline(mesh, wl["N"], u0.cpu().numpy(), dt)
+        out["cpu_baseline"] = cpu_baseline(mesh, wl["N"], u0_np, dt)
         log(f"cpu baseline in {time.time() - t0:.1f}s")
     print(json.dumps(out), flush=True)
     return 0
