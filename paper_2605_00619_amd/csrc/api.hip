@@ -295,7 +295,7 @@ afe_status launch_round(Engine &E, int it, const std::vector<int> &upper, int pr
         a.count = gr.counts + cur;
         a.next = gr.lists + size_t(nxt) * gr.cells;
         a.next_count = gr.counts + nxt;
-        a.n_upper = upper.empty() ? int(gr.cells) : upper[gi];
+        a.n_upper = upper.empty() ? -1 : upper[gi];
         a.max_cell_dofs = gr.max_cell_dofs;
         a.max_cell_subtets = gr.max_cell_subtets;
         a.shape = gr.shape;

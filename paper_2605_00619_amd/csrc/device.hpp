@@ -123,7 +123,8 @@ hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, int slot, int32_
 hipError_t launch_set_count(int32_t *count, int value, hipStream_t s);
 // One predictor iteration over the listed (slot, cell) entries of one group
 // of slots with the same degree and precision.  n_upper bounds the list
-// length (used when a grid is not persistent); max_cell_dofs and
+// length (grids are sized from it, persistent ones capped by it; -1 when
+// unknown, which needs persistent grids); max_cell_dofs and
 // max_cell_subtets are maxima over the group.
 struct RoundArgs {
     int N, mixed;

@@ -427,9 +427,11 @@ __global__ void k_set_double(double *p, double v) {
 
 // Nodal flux of the Navier-Stokes equations at node m of a sub-tet for one
 // time node (gradient from the reference derivatives when mu_c != 0) and its
-// contravariant form f*_d = dt sum_x G[d][x] F_x (eq:modified_fluxes).
+// contravariant form f*_d = dt sum_x G[d][x] F_x (eq:modified_fluxes).  Dt
+// holds D^ transposed, D^_d[m][p] at Dt[(d np + p) np + m], so that the lanes
+// of one sub-tet (consecutive m) read consecutive LDS words.
 template <int N>
-__device__ inline void node_flux(const double *Ds, const double (*qn)[5], int m, const double G[9], const double q[5],
+__device__ inline void node_flux(const double *Dt, const double (*qn)[5], int m, const double G[9], const double q[5],
                                  double gamma, double mu_c, double dt, double *fstar, double F[3][5]) {
     constexpr int np = Dim<N>::np;
     double gq[3][5] = {};
@@ -437,7 +439,7 @@ __device__ inline void node_flux(const double *Ds, const double (*qn)[5], int m,
         double rg[3][5] = {};
         for (int d = 0; d < 3; ++d)
             for (int p = 0; p < np; ++p) {
-                const double dd = Ds[(d * np + m) * np + p];
+                const double dd = Dt[(d * np + p) * np + m];
                 for (int v = 0; v < 5; ++v) rg[d][v] += dd * qn[p][v];
             }
         for (int x = 0; x < 3; ++x)
@@ -461,9 +463,9 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
                                                                    const int32_t *__restrict__ count, int chunks,
                                                                    int32_t *next_count) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
-    __shared__ double Ks[3 * np * np];
-    __shared__ double Ds[3 * np * np];
-    __shared__ double Ms[np * np];
+    __shared__ double Kt[3 * np * np];  // reference matrices transposed: (d, m, p) at (d np + p) np + m
+    __shared__ double Dt[3 * np * np];
+    __shared__ double Mt[np * np];
     __shared__ double qs[spb][nt][np][5];
     __shared__ double fs[spb][nt][np][15];
     __shared__ double us[spb][np][5];
@@ -484,10 +486,11 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
         if (chunk >= nchunk) continue;
         const bool mixed = g.mixed != 0;
         if (!loaded) {
-            for (int t = tid; t < np * np; t += blockDim.x) Ms[t] = g.ref->M[t];
+            for (int t = tid; t < np * np; t += blockDim.x) Mt[(t % np) * np + t / np] = g.ref->M[t];
             for (int t = tid; t < 3 * np * np; t += blockDim.x) {
-                Ks[t] = g.ref->K[t];
-                Ds[t] = g.ref->D[t];
+                const int d = t / (np * np), mm = (t / np) % np, p = t % np;
+                Kt[(d * np + p) * np + mm] = g.ref->K[t];
+                Dt[(d * np + p) * np + mm] = g.ref->D[t];
             }
             loaded = true;
         }
@@ -511,7 +514,7 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
         __syncthreads();
         if (valid) {
             double F[3][5];
-            node_flux<N>(Ds, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
+            node_flux<N>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
         }
         if (mixed) {
             __syncthreads();
@@ -519,7 +522,7 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
             double t[5] = {0, 0, 0, 0, 0};
             if (valid)
                 for (int p = 0; p < np; ++p) {
-                    const double mm = Ms[m * np + p];
+                    const double mm = Mt[p * np + m];
                     for (int v = 0; v < 5; ++v) t[v] += mm * (qs[s][a][p][v] - us[s][p][v]);
                 }
             for (int v = 0; v < 5; ++v) mt[s < spb ? s : 0][a][m][v] = valid ? t[v] : 0.0;
@@ -529,7 +532,7 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
             double r[5] = {0, 0, 0, 0, 0};
             for (int d = 0; d < 3; ++d)
                 for (int p = 0; p < np; ++p) {
-                    const double kk = Ks[(d * np + m) * np + p];
+                    const double kk = Kt[(d * np + p) * np + m];
                     for (int v = 0; v < 5; ++v) r[v] += kk * fs[s][a][p][d * 5 + v];
                 }
             const double sc = g.ref->w[a] * dj;
@@ -585,15 +588,15 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr int nf = Dim<N>::nf;
     __shared__ double Ks[3 * np * np];
-    __shared__ double Ds[3 * np * np];
+    __shared__ double Dt[3 * np * np];  // D^ transposed, as node_flux reads it
     __shared__ double qs[spb][nt][np][5];
-    __shared__ double fs[spb][nt][np][15];
-    __shared__ double Fs[spb][nt][np][15];
+    __shared__ double fs[spb][nt][np][15];  // f*, then (once fbar is formed) the physical fluxes F
     __shared__ double fbar[spb][np][15];
     const int tid = threadIdx.x;
     for (int t = tid; t < 3 * np * np; t += blockDim.x) {
         Ks[t] = g.ref->K[t];
-        Ds[t] = g.ref->D[t];
+        const int d = t / (np * np), mm = (t / np) % np, p = t % np;
+        Dt[(d * np + p) * np + mm] = g.ref->D[t];
     }
     const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
     const int64_t k = int64_t(blockIdx.x) * spb + s;
@@ -613,12 +616,8 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
         }
     }
     __syncthreads();
-    if (valid) {
-        double F[3][5];
-        node_flux<N>(Ds, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
-        for (int x = 0; x < 3; ++x)
-            for (int v = 0; v < 5; ++v) Fs[s][a][m][x * 5 + v] = F[x][v];
-    }
+    double F[3][5];
+    if (valid) node_flux<N>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
     __syncthreads();
     if (valid && a == 0) {
         for (int i = 0; i < 15; ++i) {
@@ -627,6 +626,10 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
             fbar[s][m][i] = acc;
         }
     }
+    __syncthreads();
+    if (valid)
+        for (int x = 0; x < 3; ++x)
+            for (int v = 0; v < 5; ++v) fs[s][a][m][x * 5 + v] = F[x][v];
     __syncthreads();
     if (!valid) return;
     if (a == 0) {
@@ -651,12 +654,14 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
             }
             for (int i = 0; i < 15; ++i) {
                 double acc = 0.0;
-                for (int b = 0; b < nt; ++b) acc += g.ref->w[b] * Fs[s][b][mm][i];
+                for (int b = 0; b < nt; ++b) acc += g.ref->w[b] * fs[s][b][mm][i];
                 out[5 + i] = dt * acc;
             }
         }
     }
 }
+
+constexpr int kMinvUnroll = 8;
 
 // Y = M_i^{-1} X for rows [64 tile, 64 tile + 64) of cell c; X and Y DOF-major
 // with NC columns.  The 4 waves of the block split the inner index j into 4
@@ -690,18 +695,15 @@ __device__ inline void minv_tile(const DevGrid &g, int c, int tile, const double
 #pragma unroll
     for (int col = 0; col < NC; ++col) acc[col] = 0.0;
     int j = j0;
-    for (; j + 4 <= j1; j += 4) {
-        const double m0 = A[int64_t(j) * ld], m1 = A[int64_t(j + 1) * ld];
-        const double m2 = A[int64_t(j + 2) * ld], m3 = A[int64_t(j + 3) * ld];
+    for (; j + kMinvUnroll <= j1; j += kMinvUnroll) {  // kMinvUnroll loads in flight per wave
+        double m[kMinvUnroll];
+#pragma unroll
+        for (int u = 0; u < kMinvUnroll; ++u) m[u] = A[int64_t(j + u) * ld];
         const cptr<double> b = B + int64_t(j) * NC;
 #pragma unroll
-        for (int col = 0; col < NC; ++col) acc[col] = fma(m0, b[col], acc[col]);
+        for (int u = 0; u < kMinvUnroll; ++u)
 #pragma unroll
-        for (int col = 0; col < NC; ++col) acc[col] = fma(m1, b[NC + col], acc[col]);
-#pragma unroll
-        for (int col = 0; col < NC; ++col) acc[col] = fma(m2, b[2 * NC + col], acc[col]);
-#pragma unroll
-        for (int col = 0; col < NC; ++col) acc[col] = fma(m3, b[3 * NC + col], acc[col]);
+            for (int col = 0; col < NC; ++col) acc[col] = fma(m[u], b[u * NC + col], acc[col]);
     }
     for (; j < j1; ++j) {
         const double m0 = A[int64_t(j) * ld];
@@ -925,22 +927,37 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
         accs[1][wv] = gmx;
     }
     if (hist_on) {
-        for (int j = 0; j <= k; ++j) {
-            const int sj = (head + j) % depth;
-            double ph = 0.0, pb = 0.0;
+        // four history columns per pass, so that their loads are in flight together
+        for (int j0 = 0; j0 <= k; j0 += 4) {
+            double ph[4], pb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ph[u] = pb[u] = 0.0;
 #pragma unroll
             for (int q = 0; q < kPer; ++q) {
                 if (ie[q] < e1) {
-                    const double d = (j == k) ? dfe[q] : dF[int64_t(sj) * len + ie[q]];
-                    ph = fma(d, dfe[q], ph);
-                    pb = fma(d, fe[q], pb);
+                    double d[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int j = j0 + u;
+                        d[u] = j < k ? dF[int64_t((head + j) % depth) * len + ie[q]] : dfe[q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ph[u] = fma(d[u], dfe[q], ph[u]);
+                        pb[u] = fma(d[u], fe[q], pb[u]);
+                    }
                 }
             }
-            ph = wave_sum(ph);
-            pb = wave_sum(pb);
-            if (lane == 0) {
-                accs[2 + j][wv] = ph;
-                accs[2 + kMaxDepth + 1 + j][wv] = pb;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int j = j0 + u;
+                if (j <= k) {
+                    const double sh = wave_sum(ph[u]), sb = wave_sum(pb[u]);
+                    if (lane == 0) {
+                        accs[2 + j][wv] = sh;
+                        accs[2 + kMaxDepth + 1 + j][wv] = sb;
+                    }
+                }
             }
         }
     }
@@ -960,9 +977,11 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
 }
 
 // One wave: w.gamma[c][0..kuse) receives the coefficients, w.kuse[c] = kuse
-// and w.hist[2c + 1] the head slot of the history.
+// and w.hist[2c + 1] the head slot of the history.  The scaled Cholesky
+// factor is worked on in LDS (Ls, logical rows): loaded with independent
+// loads, updated there, and its changed rows written back.
 __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c, int32_t entry, int32_t *next,
-                                      int32_t *next_count) {
+                                      int32_t *next_count, double (*Ls)[kMaxDepth]) {
     const int lane = threadIdx.x;
     const int n = int(g.dof_ptr[c + 1] - g.dof_ptr[c]);
     const int ntile = (n + 63) / 64;
@@ -1010,16 +1029,20 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
             const double rhs = (lane < i) ? Hc[si * kMaxDepth + sl] * dsc[si] * dsc[sl] : 0.0;
             double y = 0.0;
             for (int r = 0; r < i; ++r) {
-                const double lrj = (lane < r) ? Lc[r * kMaxDepth + lane] : 0.0;
+                const double lrj = (lane < r) ? Ls[r][lane] : 0.0;
                 const double sm = wave_sum(lrj * y);
-                const double yr = (__shfl(rhs, r, kWave) - sm) / Lc[r * kMaxDepth + r];
+                const double yr = (__shfl(rhs, r, kWave) - sm) / Ls[r][r];
                 if (lane == r) y = yr;
             }
             const double ysq = wave_sum(lane < i ? y * y : 0.0);
-            if (lane < i) Lc[i * kMaxDepth + lane] = y;
-            if (lane == 0) Lc[i * kMaxDepth + i] = sqrt(fmax(1.0 + 1e-12 - ysq, 1e-10));
-            __threadfence_block();
+            if (lane < i) Ls[i][lane] = y;
+            if (lane == 0) Ls[i][i] = sqrt(fmax(1.0 + 1e-12 - ysq, 1e-10));
+            __syncthreads();
         }
+    } else {
+        for (int i = 0; i < k; ++i)
+            if (lane <= i) Ls[i][lane] = Lc[i * kMaxDepth + lane];
+        __syncthreads();
     }
     // reduced dots: h_j = <dF_j, dF_new>, b_j = <dF_j, f>, j = 0..k (k = new column)
     double hj = 0.0, bj_raw = 0.0;
@@ -1037,9 +1060,9 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
     const double rhs = (lane < k) ? hj * dj * dk : 0.0;
     double y = 0.0;
     for (int i = 0; i < k; ++i) {
-        const double lij = (lane < i) ? Lc[i * kMaxDepth + lane] : 0.0;
+        const double lij = (lane < i) ? Ls[i][lane] : 0.0;
         const double sm = wave_sum(lij * y);
-        const double yi = (__shfl(rhs, i, kWave) - sm) / Lc[i * kMaxDepth + i];
+        const double yi = (__shfl(rhs, i, kWave) - sm) / Ls[i][i];
         if (lane == i) y = yi;
     }
     const double ysq = wave_sum(lane < k ? y * y : 0.0);
@@ -1048,42 +1071,48 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
     const int kuse = add ? k + 1 : k;
     if (add) {
         if (lane < k) {
-            Lc[k * kMaxDepth + lane] = y;
             Hc[snew * kMaxDepth + sl] = hj;
             Hc[sl * kMaxDepth + snew] = hj;
         }
         if (lane == 0) {
-            Lc[k * kMaxDepth + k] = sqrt(diag);
             Hc[snew * kMaxDepth + snew] = hkk;
             dsc[snew] = dk;
         }
     }
-    __threadfence_block();
     const double scl = (lane < k) ? dj : ((lane == k) ? dk : 0.0);
     const double bj = (lane < kuse) ? bj_raw * scl : 0.0;
     double z = 0.0;
     for (int i = 0; i < kuse; ++i) {
-        const double lij = (lane < i) ? ((i == k) ? y : Lc[i * kMaxDepth + lane]) : 0.0;
+        const double lij = (lane < i) ? ((i == k) ? y : Ls[i][lane]) : 0.0;
         const double sm = wave_sum(lij * z);
-        const double lii = (i == k) ? sqrt(diag) : Lc[i * kMaxDepth + i];
+        const double lii = (i == k) ? sqrt(diag) : Ls[i][i];
         const double zi = (__shfl(bj, i, kWave) - sm) / lii;
         if (lane == i) z = zi;
     }
     double xs = 0.0;
     for (int i = kuse - 1; i >= 0; --i) {
         const double yi_new = __shfl(y, i, kWave);  // L[k][i] of the new row
-        const double lji = (lane > i && lane < kuse) ? ((lane == k) ? yi_new : Lc[lane * kMaxDepth + i]) : 0.0;
+        const double lji = (lane > i && lane < kuse) ? ((lane == k) ? yi_new : Ls[lane < k ? lane : 0][i]) : 0.0;
         const double sm = wave_sum(lji * xs);
-        const double lii = (i == k) ? sqrt(diag) : Lc[i * kMaxDepth + i];
+        const double lii = (i == k) ? sqrt(diag) : Ls[i][i];
         const double xi = (__shfl(z, i, kWave) - sm) / lii;
         if (lane == i) xs = xi;
     }
     if (lane < kuse) gam[lane] = xs * scl;
+    // write back the rows that changed: all after a rebuild, else the new one
+    if (dropped)
+        for (int i = 0; i < k; ++i)
+            if (lane <= i) Lc[i * kMaxDepth + lane] = Ls[i][lane];
+    if (add) {
+        if (lane < k) Lc[k * kMaxDepth + lane] = y;
+        if (lane == 0) Lc[k * kMaxDepth + k] = sqrt(diag);
+    }
     if (lane == 0) {
         w.kuse[c] = kuse;
         w.hist[2 * c] = kuse;
         w.hist[2 * c + 1] = head;
     }
+    __syncthreads();  // Ls is reused by the next item
 }
 
 template <int N>
@@ -1106,12 +1135,13 @@ __global__ void __launch_bounds__(256) k_round_dots(const DevSlot *__restrict__ 
 __global__ void __launch_bounds__(64) k_round_solve(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
                                                     const int32_t *__restrict__ count, int32_t *next,
                                                     int32_t *next_count) {
+    __shared__ double Ls[kMaxDepth][kMaxDepth];
     const int n_items = *count;
     for (int item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int32_t entry = list[item];
         int slot, c;
         decode(entry, slot, c);
-        and_solve_cell(tab[slot].g, tab[slot].w, c, entry, next, next_count);
+        and_solve_cell(tab[slot].g, tab[slot].w, c, entry, next, next_count, Ls);
     }
 }
 
@@ -1134,13 +1164,21 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
         const int kuse = w.kuse[c];
         const int depth = w.depth;
         const int head = w.hist[2 * c + 1];
-        const double *gam = w.gamma + int64_t(c) * kMaxDepth;
+        const cptr<double> gam = (cptr<double>)uni_ptr(w.gamma + int64_t(c) * kMaxDepth);
         const double *dG = w.dG + base * (depth > 0 ? depth : 1);
         const int64_t e0 = int64_t(tile) * 64 * nc;
         const int64_t e1 = min(len, e0 + int64_t(64) * nc);
         for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
             double xv = w.gprev[base + e];
-            for (int j = 0; j < kuse; ++j) xv -= gam[j] * dG[int64_t((head + j) % depth) * len + e];
+            int j = 0;
+            for (; j + 4 <= kuse; j += 4) {
+                double d[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) d[u] = dG[int64_t((head + j + u) % depth) * len + e];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) xv -= gam[j + u] * d[u];
+            }
+            for (; j < kuse; ++j) xv -= gam[j] * dG[int64_t((head + j) % depth) * len + e];
             w.x[base + e] = xv;
         }
     }
@@ -1382,9 +1420,12 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
         using D = Dim<NN>;
         const int chunks = (a.max_cell_subtets + D::spb - 1) / D::spb;
         const int tpc = (a.max_cell_dofs + 63) / 64;
-        // persistent grid, or one workgroup per item of the longest possible list
+        // one workgroup per item of the longest possible list, at most the
+        // persistent grid (n_upper < 0: length unknown, graph capture)
         auto grid = [&](int persistent, int per) {
-            return dim3(persistent > 0 ? unsigned(persistent) : unsigned(std::max(1, a.n_upper * per)));
+            if (a.n_upper < 0) return dim3(unsigned(persistent));
+            const int items = std::max(1, a.n_upper * per);
+            return dim3(unsigned(persistent > 0 ? std::min(persistent, items) : items));
         };
         const int per = int((int64_t(a.max_cell_dofs) * D::nc + 255) / 256);
         hipLaunchKernelGGL(k_round_subtet<NN>, grid(a.shape.g_sub, chunks), dim3(D::threads), 0, s, a.tab, a.list,
