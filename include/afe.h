@@ -202,7 +202,8 @@ afe_status afe_estimate_bytes(const afe_mesh *mesh, int32_t N, const afe_params 
  * A batch steps several simulations (cell-data objects, each with its own
  * mesh, degree, parameters and state) together: one ADER step of every
  * attached simulation per afe_batch_step.  The predictor iterations of all
- * simulations with the same degree and precision share each kernel launch
+ * simulations with the same degree, precision and viscosity (physical or
+ * artificial, or none) share each kernel launch
  * (their cells are packed into one list of (simulation, cell) entries, cells
  * of uneven size included); the time step of each simulation comes from its
  * own CFL number and state (eqn.timestep) and stays on the device.  Results

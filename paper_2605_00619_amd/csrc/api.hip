@@ -10,6 +10,7 @@
 #include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/afe.h"
@@ -40,10 +41,14 @@ afe_status fail(afe_status s, const std::string &msg) {
 
 constexpr int kStatusWords = 8;
 
-// One group of slots with the same degree and precision: they share the
-// predictor's launches through one list of (slot, cell) entries.
+// One group of slots with the same degree, precision and viscosity (physical
+// or artificial, or none): they share the predictor's launches through one
+// list of (slot, cell) entries.  A simulation always runs the same kernel
+// instances, whatever it is batched with, so its results do not depend on
+// its batch-mates.
 struct Group {
     int N = 0, mixed = 0;
+    int visc = 0;
     std::vector<int> slots;
     std::vector<int64_t> base;  // list offset of each slot's cells
     int64_t cells = 0;
@@ -215,21 +220,22 @@ afe_status sync_layout(Engine &E, hipStream_t s) {
     HIP_TRY(hipStreamSynchronize(s));
     E.drop_graphs();
     E.drop_groups();
-    std::map<std::pair<int, int>, int> gid;
+    std::map<std::tuple<int, int, int>, int> gid;
     for (int sl = 0; sl < afe::kMaxSlots; ++sl) {
         afe_cell_data *cd = E.cds[sl];
         if (!cd) continue;
         E.tab[sl].g = cd->g;
         E.tab[sl].w = cd->w;
         E.tab[sl].w.u = E.u[sl];
-        const auto key = std::make_pair(cd->g.N, cd->g.mixed);
+        const int visc = (cd->g.mu != 0.0 || cd->g.av) ? 1 : 0;
+        const auto key = std::make_tuple(cd->g.N, cd->g.mixed, visc);
         auto it = gid.find(key);
         if (it == gid.end()) {
             it = gid.emplace(key, int(E.groups.size())).first;
             Group gr;
-            gr.N = key.first;
-            gr.mixed = key.second;
-            gr.resident = afe::resident_shape(gr.N, gr.mixed);
+            gr.N = cd->g.N;
+            gr.mixed = cd->g.mixed;
+            gr.visc = visc;
             E.groups.push_back(gr);
         }
         Group &gr = E.groups[it->second];
@@ -240,6 +246,7 @@ afe_status sync_layout(Engine &E, hipStream_t s) {
         gr.max_cell_subtets = std::max(gr.max_cell_subtets, cd->host.max_cell_subtets);
     }
     for (auto &gr : E.groups) {
+        gr.resident = afe::resident_shape(gr.N, gr.mixed, gr.visc);
         if (gr.cells > INT_MAX / 64) return fail(AFE_E_ARG, "too many cells in one group");
         HIP_TRY(hipMalloc(&gr.lists, sizeof(int32_t) * 2 * size_t(gr.cells)));
         HIP_TRY(hipMalloc(&gr.counts, sizeof(int32_t) * 2));
@@ -290,6 +297,7 @@ afe_status launch_round(Engine &E, int it, const std::vector<int> &upper, int pr
         afe::RoundArgs a{};
         a.N = gr.N;
         a.mixed = gr.mixed;
+        a.visc = gr.visc;
         a.tab = E.d_tab;
         a.list = gr.lists + size_t(cur) * gr.cells;
         a.count = gr.counts + cur;

@@ -127,7 +127,7 @@ hipError_t launch_set_count(int32_t *count, int value, hipStream_t s);
 // unknown, which needs persistent grids); max_cell_dofs and
 // max_cell_subtets are maxima over the group.
 struct RoundArgs {
-    int N, mixed;
+    int N, mixed, visc;
     const DevSlot *tab;
     const int32_t *list, *count;
     int32_t *next, *next_count;
@@ -141,8 +141,8 @@ hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, hipStream_t s);
 hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, hipStream_t s);
 // Predictor iteration counts of the step into status[4..7].
 hipError_t launch_step_stats(const DevGrid &g, const DevWork &w, hipStream_t s);
-// Occupancy-derived persistent grid sizes for degree N (workgroups that fit
-// on the device at once, per kernel).
-IterShape resident_shape(int N, int mixed);
+// Occupancy-derived persistent grid sizes for degree N, precision and
+// viscosity (workgroups that fit on the device at once, per kernel).
+IterShape resident_shape(int N, int mixed, int visc);
 
 }  // namespace afe

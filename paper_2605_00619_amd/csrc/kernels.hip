@@ -430,12 +430,13 @@ __global__ void k_set_double(double *p, double v) {
 // contravariant form f*_d = dt sum_x G[d][x] F_x (eq:modified_fluxes).  Dt
 // holds D^ transposed, D^_d[m][p] at Dt[(d np + p) np + m], so that the lanes
 // of one sub-tet (consecutive m) read consecutive LDS words.
-template <int N>
+template <int N, bool VISC>
 __device__ inline void node_flux(const double *Dt, const double (*qn)[5], int m, const double G[9], const double q[5],
                                  double gamma, double mu_c, double dt, double *fstar, double F[3][5]) {
     constexpr int np = Dim<N>::np;
     double gq[3][5] = {};
-    if (mu_c != 0.0) {
+    if (!VISC) mu_c = 0.0;  // inviscid group: no cell viscosity
+    if (VISC && mu_c != 0.0) {
         double rg[3][5] = {};
         for (int d = 0; d < 3; ++d)
             for (int p = 0; p < np; ++p) {
@@ -456,20 +457,22 @@ __device__ inline void node_flux(const double *Dt, const double (*qn)[5], int m,
 // rk[a][m] = w_a |J| sum_d sum_p K^_d[m][p] f*_d[a][p] (eq:ader4); in mixed
 // precision the sub-tet's part of (K_tau (x) M_i)(q - 1 (x) u^n) is added,
 // which makes rk the unpreconditioned residual of eq:ADER-localCauchy.
-// Block 0 clears the next list's length.
-template <int N>
+// Block 0 clears the next list's length.  VISC: some simulation of the group
+// has a physical or artificial viscosity; MIXED: the group's precision.
+template <int N, bool VISC, bool MIXED>
 __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_per_eu(2))) k_round_subtet(const DevSlot *__restrict__ tab,
                                                                    const int32_t *__restrict__ list,
                                                                    const int32_t *__restrict__ count, int chunks,
                                                                    int32_t *next_count) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
+    constexpr int nd = VISC ? 3 * np * np : 1, nm = MIXED ? np * np : 1, sm = MIXED ? spb : 1;
     __shared__ double Kt[3 * np * np];  // reference matrices transposed: (d, m, p) at (d np + p) np + m
-    __shared__ double Dt[3 * np * np];
-    __shared__ double Mt[np * np];
+    __shared__ double Dt[nd];
+    __shared__ double Mt[nm];
     __shared__ double qs[spb][nt][np][5];
     __shared__ double fs[spb][nt][np][15];
-    __shared__ double us[spb][np][5];
-    __shared__ double mt[spb][nt][np][5];  // M^ (q_b - u^n) per time node
+    __shared__ double us[sm][np][5];
+    __shared__ double mt[sm][nt][np][5];  // M^ (q_b - u^n) per time node
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     const int tid = threadIdx.x;
     const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
@@ -484,13 +487,13 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
         const int nchunk = int((s1 - s0 + spb - 1) / spb);
         const int chunk = item % chunks;
         if (chunk >= nchunk) continue;
-        const bool mixed = g.mixed != 0;
         if (!loaded) {
-            for (int t = tid; t < np * np; t += blockDim.x) Mt[(t % np) * np + t / np] = g.ref->M[t];
+            if (MIXED)
+                for (int t = tid; t < np * np; t += blockDim.x) Mt[MIXED ? (t % np) * np + t / np : 0] = g.ref->M[t];
             for (int t = tid; t < 3 * np * np; t += blockDim.x) {
                 const int d = t / (np * np), mm = (t / np) % np, p = t % np;
                 Kt[(d * np + p) * np + mm] = g.ref->K[t];
-                Dt[(d * np + p) * np + mm] = g.ref->D[t];
+                if (VISC) Dt[VISC ? (d * np + p) * np + mm : 0] = g.ref->D[t];
             }
             loaded = true;
         }
@@ -508,24 +511,24 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
                 q[v] = w.x[l * nc + a * 5 + v];
                 qs[s][a][m][v] = q[v];
             }
-            if (mixed && a == 0)
-                for (int v = 0; v < 5; ++v) us[s][m][v] = w.u[v * g.ndof + l];
+            if (MIXED && a == 0)
+                for (int v = 0; v < 5; ++v) us[MIXED ? s : 0][m][v] = w.u[v * g.ndof + l];
         }
         __syncthreads();
         if (valid) {
             double F[3][5];
-            node_flux<N>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
+            node_flux<N, VISC>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
         }
-        if (mixed) {
+        if (MIXED) {
             __syncthreads();
             // thread (s, b = a, m): the sub-tet mass product of time node b
             double t[5] = {0, 0, 0, 0, 0};
             if (valid)
                 for (int p = 0; p < np; ++p) {
-                    const double mm = Mt[p * np + m];
-                    for (int v = 0; v < 5; ++v) t[v] += mm * (qs[s][a][p][v] - us[s][p][v]);
+                    const double mm = Mt[MIXED ? p * np + m : 0];
+                    for (int v = 0; v < 5; ++v) t[v] += mm * (qs[s][a][p][v] - us[MIXED ? s : 0][p][v]);
                 }
-            for (int v = 0; v < 5; ++v) mt[s < spb ? s : 0][a][m][v] = valid ? t[v] : 0.0;
+            for (int v = 0; v < 5; ++v) mt[MIXED ? s : 0][a][m][v] = valid ? t[v] : 0.0;
         }
         __syncthreads();
         if (valid) {
@@ -537,11 +540,11 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
                 }
             const double sc = g.ref->w[a] * dj;
             double *out = w.rk + (k * np + m) * nc + a * 5;
-            if (mixed) {
+            if (MIXED) {
                 double mr[5] = {0, 0, 0, 0, 0};
                 for (int b = 0; b < nt; ++b) {
                     const double kt = g.ref->Ktau[a * nt + b];
-                    for (int v = 0; v < 5; ++v) mr[v] += kt * mt[s][b][m][v];
+                    for (int v = 0; v < 5; ++v) mr[v] += kt * mt[MIXED ? s : 0][b][m][v];
                 }
                 for (int v = 0; v < 5; ++v) out[v] = sc * r[v] + dj * mr[v];
             } else {
@@ -583,12 +586,12 @@ __global__ void __launch_bounds__(256) k_round_gather(const DevSlot *__restrict_
 // Time integrals of the converged predictor, all sub-tets of one simulation:
 // the volume term |J| sum_d V^_d F*bar_d (Sec. 4.4) and the face traces
 // (qbar, Fbar) at the boundary-triangle nodes.
-template <int N>
+template <int N, bool VISC>
 __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevWork w) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr int nf = Dim<N>::nf;
     __shared__ double Ks[3 * np * np];
-    __shared__ double Dt[3 * np * np];  // D^ transposed, as node_flux reads it
+    __shared__ double Dt[VISC ? 3 * np * np : 1];  // D^ transposed, as node_flux reads it
     __shared__ double qs[spb][nt][np][5];
     __shared__ double fs[spb][nt][np][15];  // f*, then (once fbar is formed) the physical fluxes F
     __shared__ double fbar[spb][np][15];
@@ -596,7 +599,7 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
     for (int t = tid; t < 3 * np * np; t += blockDim.x) {
         Ks[t] = g.ref->K[t];
         const int d = t / (np * np), mm = (t / np) % np, p = t % np;
-        Dt[(d * np + p) * np + mm] = g.ref->D[t];
+        if (VISC) Dt[VISC ? (d * np + p) * np + mm : 0] = g.ref->D[t];
     }
     const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
     const int64_t k = int64_t(blockIdx.x) * spb + s;
@@ -617,7 +620,7 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
     }
     __syncthreads();
     double F[3][5];
-    if (valid) node_flux<N>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
+    if (valid) node_flux<N, VISC>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
     __syncthreads();
     if (valid && a == 0) {
         for (int i = 0; i < 15; ++i) {
@@ -1428,8 +1431,10 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
             return dim3(unsigned(persistent > 0 ? std::min(persistent, items) : items));
         };
         const int per = int((int64_t(a.max_cell_dofs) * D::nc + 255) / 256);
-        hipLaunchKernelGGL(k_round_subtet<NN>, grid(a.shape.g_sub, chunks), dim3(D::threads), 0, s, a.tab, a.list,
-                           a.count, chunks, a.next_count);
+        auto sub = a.visc ? (a.mixed ? k_round_subtet<NN, true, true> : k_round_subtet<NN, true, false>)
+                          : (a.mixed ? k_round_subtet<NN, false, true> : k_round_subtet<NN, false, false>);
+        hipLaunchKernelGGL(sub, grid(a.shape.g_sub, chunks), dim3(D::threads), 0, s, a.tab, a.list, a.count, chunks,
+                           a.next_count);
         hipLaunchKernelGGL(k_round_gather<NN>, grid(a.shape.g_gather, per), dim3(256), 0, s, a.tab, a.list, a.count,
                            per);
         if (a.ev0) (void)hipEventRecord(a.ev0, s);
@@ -1453,7 +1458,11 @@ hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, hipStream_t s) {
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        hipLaunchKernelGGL(k_subtet_post<NN>, dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w);
+        if (g.mu != 0.0 || g.av)
+            hipLaunchKernelGGL((k_subtet_post<NN, true>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w);
+        else
+            hipLaunchKernelGGL((k_subtet_post<NN, false>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g,
+                               w);
         return hipGetLastError();
     });
 }
@@ -1476,7 +1485,7 @@ hipError_t launch_step_stats(const DevGrid &g, const DevWork &w, hipStream_t s) 
     return hipGetLastError();
 }
 
-IterShape resident_shape(int N, int mixed) {
+IterShape resident_shape(int N, int mixed, int visc) {
     IterShape sh;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -1488,7 +1497,11 @@ IterShape resident_shape(int N, int mixed) {
     (void)dispatch(N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        sh.g_sub = fit(reinterpret_cast<const void *>(&k_round_subtet<NN>), D::threads);
+        sh.g_sub = fit(visc ? (mixed ? reinterpret_cast<const void *>(&k_round_subtet<NN, true, true>)
+                                     : reinterpret_cast<const void *>(&k_round_subtet<NN, true, false>))
+                            : (mixed ? reinterpret_cast<const void *>(&k_round_subtet<NN, false, true>)
+                                     : reinterpret_cast<const void *>(&k_round_subtet<NN, false, false>)),
+                       D::threads);
         sh.g_gather = fit(reinterpret_cast<const void *>(&k_round_gather<NN>), 256);
         sh.g_minv = mixed ? fit(reinterpret_cast<const void *>(&k_round_minv32<D::nc>), 256)
                           : fit(reinterpret_cast<const void *>(&k_round_minv<D::nc>), 256);

@@ -26,21 +26,24 @@ def _sphere(x):
     return smoothed_sphere(x, 0.3, 0.05)
 
 
-# (seeds per side, jitter, seed, N, mixed, field, cfl): uneven cell counts
-# (27 to 125 cells), all three degrees, both precisions, two states
+# (seeds per side, jitter, seed, N, mixed, field, cfl, viscosity): uneven
+# cell counts (27 to 125 cells), all three degrees, both precisions, two
+# states; the last case is viscous, so that its degree group runs the viscous
+# kernels for the inviscid case of the same degree too
 CASES = [
-    (3, 0.2, 0, 1, False, density_wave, 0.01),
-    (4, 0.2, 0, 2, False, density_wave, 0.004),
-    (5, 0.25, 3, 2, False, _sphere, 0.004),
-    (4, 0.25, 5, 3, True, density_wave, 0.004),
-    (4, 0.2, 7, 3, False, _sphere, 0.004),
+    (3, 0.2, 0, 1, False, density_wave, 0.01, 0.0),
+    (4, 0.2, 0, 2, False, density_wave, 0.004, 0.0),
+    (5, 0.25, 3, 2, False, _sphere, 0.004, 0.0),
+    (4, 0.25, 5, 3, True, density_wave, 0.004, 0.0),
+    (4, 0.2, 7, 3, False, _sphere, 0.004, 0.0),
+    (4, 0.2, 9, 2, False, density_wave, 0.004, 2e-3),
 ]
 
 
 def _build(afe, case, tol=1e-12):
-    n, jit, seed, N, mixed, field, cfl = case
+    n, jit, seed, N, mixed, field, cfl, mu = case
     mesh = periodic_voronoi(jittered_lattice_seeds(n, jit, seed))
-    cd = afe.CellData(mesh, N, afe.Params(tol=tol, precision=afe.AFE_MIXED if mixed else afe.AFE_FP64))
+    cd = afe.CellData(mesh, N, afe.Params(tol=tol, mu=mu, precision=afe.AFE_MIXED if mixed else afe.AFE_FP64))
     x = cd.dof_coords().cpu().numpy()
     prim = torch.tensor(field(np.mod(x.T, 1.0)).T.copy(), device="cuda")
     return mesh, cd, cd.prim_to_cons(prim), cfl
@@ -59,9 +62,10 @@ def _run(afe, cases, steps, shape=None):
 
 
 def test_batch_alone_equals_mixed():
-    """Each simulation stepped in a batch with four others (packed cells of
-    uneven counts, mixed degrees and precisions) gives bit for bit the state
-    it reaches alone, and the same time steps and iteration counts."""
+    """Each simulation stepped in a batch with five others (packed cells of
+    uneven counts, mixed degrees, precisions and viscosities) gives bit for
+    bit the state it reaches alone, and the same time steps and iteration
+    counts."""
     afe = _lib()
     mixed_u, mixed_r = _run(afe, CASES, steps=2)
     for i, case in enumerate(CASES):
@@ -115,15 +119,15 @@ def test_batch_step_matches_oracle():
     the oracle's step at the oracle's own CFL time step."""
     from oracle.scheme import Oracle, Params
     afe = _lib()
-    tol = 1e-13
+    tol = 1e-14  # both sides, far below the bar (the fixed point is defined up to the stop test)
     mesh = periodic_voronoi(jittered_lattice_seeds(4, 0.2, 0))
-    o = Oracle(mesh, 2, Params(tol=tol))
+    o = Oracle(mesh, 2, Params(tol=tol, max_iter=600))
     u0 = o.initial_state(density_wave)
     dt = o.cfl_dt(u0, 0.004)
     uo, rep = o.step(u0, dt)
     assert rep.converged
     other = _build(afe, CASES[0])
-    cd = afe.CellData(mesh, 2, afe.Params(tol=tol))
+    cd = afe.CellData(mesh, 2, afe.Params(tol=tol, max_iter=600))
     ug = torch.tensor(u0, device="cuda")
     b = afe.Batch()
     b.attach(other[1], other[2], other[3])
@@ -155,9 +159,9 @@ def test_estimate_bytes_matches_allocation():
     object allocates, up to the allocator's per-buffer minimum."""
     afe = _lib()
     for case in CASES:
-        n, jit, seed, N, mixed, _, _ = case
+        n, jit, seed, N, mixed, _, _, mu = case
         mesh = periodic_voronoi(jittered_lattice_seeds(n, jit, seed))
-        p = afe.Params(precision=afe.AFE_MIXED if mixed else afe.AFE_FP64)
+        p = afe.Params(mu=mu, precision=afe.AFE_MIXED if mixed else afe.AFE_FP64)
         est = afe.estimate_bytes(mesh, N, p)
         cd = afe.CellData(mesh, N, p)
         assert abs(est - cd.device_bytes) <= 0.02 * cd.device_bytes, (case, est, cd.device_bytes)

@@ -26,14 +26,22 @@ def rel_linf(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-TOL = 1e-13  # predictor stop on both sides, below the 1e-12 parity bar
+# Predictor stop on both sides.  The predictor is a fixed point defined up to
+# its stop test; a step amplifies that ambiguity (density wave, 4^3 seeds,
+# N = 2: 1.25e-12 apart at a stop of 1e-13, 2.8e-13 at 3e-14, 7.5e-14 at
+# 1e-14), so parity is checked with both sides stopping at 1e-14, well below
+# the 1e-12 bar.
+TOL = 1e-14
+# The artificial-viscosity case keeps 1e-13: its bar is derived from the
+# oracle's own spread at that stop (see oracle_spread).
+TOL_AV = 1e-13
 
 
 def _run_both(mesh, N, field, steps, cfl, params_o, params_g, dt=None):
     from oracle.scheme import Oracle
     afe = _lib()
-    params_o.tol = TOL
-    params_g.tol = TOL
+    params_o.tol = params_g.tol = TOL
+    params_o.max_iter = params_g.max_iter = 600
     o = Oracle(mesh, N, params_o)
     u0 = o.initial_state(field)
     cd = afe.CellData(mesh, N, params_g)
@@ -98,7 +106,7 @@ def oracle_spread(mesh, N, u0, dt, steps, uref, **kw):
     the stopping test leaves along the stiffest modes."""
     from oracle.scheme import Oracle, Params
     spread = 0.0
-    for extra in (dict(depth=48, tol=TOL), dict(tol=TOL / 3)):
+    for extra in (dict(depth=48, tol=TOL_AV), dict(tol=TOL_AV / 3)):
         o = Oracle(mesh, N, Params(max_iter=600, **{**kw, **extra}))
         u = u0
         for _ in range(steps):
@@ -117,7 +125,7 @@ def test_step_parity_with_artificial_viscosity(mesh_4):
     from oracle.physics import prim_to_cons
     from oracle.scheme import Oracle, Params
     afe = _lib()
-    o = Oracle(mesh_4, 2, Params(av=True, tol=TOL))
+    o = Oracle(mesh_4, 2, Params(av=True, tol=TOL_AV))
     seeds = mesh_4["seeds"]
     u0 = np.zeros((5, o.ndof))
     for c in range(o.n_cells):
@@ -126,7 +134,7 @@ def test_step_parity_with_artificial_viscosity(mesh_4):
         w = np.array([1.0, 0.0, 0.0, 0.0, 1.0]) if r >= 0.3 else np.array([1.0, *(0.2 * d / r), 1.0])
         u0[:, o.dof_ptr[c]:o.dof_ptr[c + 1]] = prim_to_cons(np.tile(w, (o.grids[c].ndof, 1)), 1.4).T
     dt = o.cfl_dt(u0, 0.004)
-    cd = afe.CellData(mesh_4, 2, afe.Params(av=True, tol=TOL))
+    cd = afe.CellData(mesh_4, 2, afe.Params(av=True, tol=TOL_AV))
     ug = torch.tensor(u0, device="cuda")
     uo = u0
     for _ in range(2):
