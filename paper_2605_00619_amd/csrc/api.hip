@@ -73,6 +73,11 @@ struct Engine {
     int32_t *h_counts = nullptr;       // pinned [kMaxSlots]
     hipStream_t own = nullptr;         // private stream (graph capture needs a non-null stream)
     hipEvent_t join[2] = {nullptr, nullptr};
+    // early time-integral pass: once few cells still iterate, the time
+    // integrals of the converged ones run on a side stream under the tail
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_early = nullptr;
+    bool forked = false;
     hipGraphExec_t g_pre = nullptr, g_post = nullptr, g_chunk[2] = {nullptr, nullptr};
     // profiling of the first group's M^{-1} launches
     bool prof_on = false;
@@ -95,6 +100,12 @@ struct Engine {
         for (auto &e : join)
             if (e) (void)hipEventDestroy(e);
         if (own) (void)hipStreamDestroy(own);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_early) (void)hipEventDestroy(ev_early);
+        if (side) {
+            (void)hipStreamSynchronize(side);
+            (void)hipStreamDestroy(side);
+        }
     }
     void drop_graphs() {
         for (hipGraphExec_t *g : {&g_pre, &g_post, &g_chunk[0], &g_chunk[1]})
@@ -185,7 +196,7 @@ size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub
     b += size_t(nsub) * nf * 25 * sizeof(double) + size_t(nsub) * np * 5 * sizeof(double);  // traces, faces, volume
     b += ndof * (5 * 8 + 8 + 4 + 8 + 4 + 4);  // rhs, column sums, DOF cell, scales, incidence offsets
     b += size_t(nsub) * (2 * np * 4 + 10 * 8 + 4 * 8 + 4 + 4 + 2 * nf * 4);  // connectivity, geometry, incidences
-    b += n_cells * ((2 * 63 * 63 + 2 * 63) * 8 + 88);  // Gram / Cholesky, coefficients, per-cell scalars and offsets
+    b += n_cells * ((2 * 63 * 63 + 2 * 63) * 8 + 92);  // Gram / Cholesky, coefficients, per-cell scalars and offsets
     b += 2 * n_cells * sizeof(int32_t);           // predictor list of a batch of one
     return b;
 }
@@ -339,6 +350,45 @@ afe_status chunk_body(Engine &E, int parity, hipStream_t s) {
     return AFE_OK;
 }
 
+afe_status ensure_side(Engine &E) {
+    if (E.side) return AFE_OK;
+    HIP_TRY(hipStreamCreateWithFlags(&E.side, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&E.ev_fork, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&E.ev_early, hipEventDisableTiming));
+    return AFE_OK;
+}
+
+// A cell's predictor is final once it has left the lists.  When at most
+// 1/kEarlyFraction of the cells still iterate, the cells of the lists for
+// iteration `it` are marked late and the time integrals of all other cells
+// are computed on the side stream, overlapping the remaining iterations;
+// finish_post joins it and computes the late cells' integrals.  The pass a
+// sub-tet falls in does not change its result.
+constexpr int64_t kEarlyFraction = 16;
+
+afe_status launch_early_post(Engine &E, int it, const std::vector<int> &upper, hipStream_t s) {
+    AFE_TRY(ensure_side(E));
+    for (auto &gr : E.groups)
+        for (int sl : gr.slots) HIP_TRY(afe::launch_clear_late(E.cds[sl]->g, E.tab[sl].w, s));
+    for (size_t gi = 0; gi < E.groups.size(); ++gi) {
+        const Group &gr = E.groups[gi];
+        HIP_TRY(afe::launch_mark_listed(E.d_tab, gr.lists + size_t(it % 2) * gr.cells, upper[gi], s));
+    }
+    HIP_TRY(hipEventRecord(E.ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(E.side, E.ev_fork, 0));
+    for (auto &gr : E.groups)
+        for (int sl : gr.slots) HIP_TRY(afe::launch_pred_post(E.cds[sl]->g, E.tab[sl].w, 0, E.side));
+    HIP_TRY(hipEventRecord(E.ev_early, E.side));
+    E.forked = true;
+    return AFE_OK;
+}
+
+// Orders s after the early pass, if one ran in this step.
+afe_status join_early(Engine &E, hipStream_t s) {
+    if (E.forked) HIP_TRY(hipStreamWaitEvent(s, E.ev_early, 0));
+    return AFE_OK;
+}
+
 // Predictor iterations until every list is empty: `rounds` iterations are
 // enqueued between two reads of the list lengths (with grids sized from the
 // lengths: one per read while lists are long).  Cells leave the lists when
@@ -352,6 +402,8 @@ afe_status iterate(Engine &E, hipStream_t s) {
     std::vector<int> upper(E.groups.size());
     int64_t total = 0;
     for (size_t gi = 0; gi < E.groups.size(); ++gi) total += upper[gi] = int(E.groups[gi].cells);
+    const int64_t all_cells = total;
+    E.forked = false;
     int it = 0;
     while (total > 0 && it < max_it) {
         int R = E.shape.rounds;
@@ -373,6 +425,7 @@ afe_status iterate(Engine &E, hipStream_t s) {
         HIP_TRY(hipStreamSynchronize(s));
         total = 0;
         for (size_t gi = 0; gi < E.groups.size(); ++gi) total += upper[gi] = E.h_counts[gi];
+        if (!E.forked && total > 0 && total * kEarlyFraction <= all_cells) AFE_TRY(launch_early_post(E, it, upper, s));
         if (E.prof_on && !graph) {
             for (int r = 0; r < std::min(R, afe::kMaxRounds); ++r) {
                 float ms = 0.0f;
@@ -392,7 +445,7 @@ afe_status launch_post(Engine &E, hipStream_t s) {
         for (int sl : gr.slots) {
             afe_cell_data *cd = E.cds[sl];
             const afe::DevWork &w = E.tab[sl].w;
-            HIP_TRY(afe::launch_pred_post(cd->g, w, s));
+            HIP_TRY(afe::launch_pred_post(cd->g, w, 1, s));
             HIP_TRY(afe::launch_correct(cd->g, w, E.u[sl], s));
             HIP_TRY(afe::launch_step_stats(cd->g, w, s));
         }
@@ -453,6 +506,7 @@ afe_status batch_step_on(Engine &E, afe_batch_report *reps, int32_t n_reps, hipS
         AFE_TRY(launch_pre(E, true, s));
     }
     AFE_TRY(iterate(E, s));
+    AFE_TRY(join_early(E, s));
     if (graph) {
         if (!E.g_post) AFE_TRY(capture(E, &E.g_post, s, post_body, 0));
         HIP_TRY(hipGraphLaunch(E.g_post, s));
@@ -645,6 +699,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(w.iters, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.gamma, size_t(h.n_cells) * 63)) != hipSuccess ||
         (e = cd->alloc(w.kuse, size_t(h.n_cells))) != hipSuccess ||
+        (e = cd->alloc(w.late, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.dt, 1)) != hipSuccess ||
         (e = cd->alloc(w.status, kStatusWords)) != hipSuccess || (e = cd->alloc(cd->d_scalar, 1)) != hipSuccess ||
         (e = hipHostMalloc(&cd->h_status, kStatusWords * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
@@ -803,7 +858,8 @@ afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *str
     HIP_TRY(afe::launch_set_dt(cd->w, dt, s));
     AFE_TRY(launch_pre(E, false, s));
     AFE_TRY(iterate(E, s));
-    HIP_TRY(afe::launch_pred_post(cd->g, E.tab[0].w, s));
+    AFE_TRY(join_early(E, s));
+    HIP_TRY(afe::launch_pred_post(cd->g, E.tab[0].w, 1, s));
     return AFE_OK;
 }
 

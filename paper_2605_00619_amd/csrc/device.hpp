@@ -74,6 +74,7 @@ struct DevWork {
     int32_t *status; // [8]: flags, first bad cell, -, troubled count, iterations min, max, sum (64 bit)
     double *gamma;   // [n_cells][63] Anderson coefficients
     int32_t *kuse;   // [n_cells] history columns used by the update
+    int32_t *late;   // [n_cells] 1: time integrals left to the final pass (still iterating at the early pass)
     double *dt;      // [1] time step of the current step
     const double *u; // state u^n of the current step, SoA [5][ndof] (caller-owned)
     double tol;      // predictor stop: max|G(q)-q| <= tol * max(1, max|G(q)|)
@@ -137,7 +138,14 @@ struct RoundArgs {
     unsigned long long *bytes;
 };
 hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s);
-hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, hipStream_t s);
+// Early time-integral pass: late[] cleared for one slot, then set for the
+// cells of the listed (slot, cell) entries (count: the list length, known on
+// the host).
+hipError_t launch_clear_late(const DevGrid &g, const DevWork &w, hipStream_t s);
+hipError_t launch_mark_listed(const DevSlot *tab, const int32_t *list, int count, hipStream_t s);
+// Time integrals of the converged predictor for the sub-tets of cells with
+// late[c] == which.
+hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, int which, hipStream_t s);
 hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, hipStream_t s);
 // Predictor iteration counts of the step into status[4..7].
 hipError_t launch_step_stats(const DevGrid &g, const DevWork &w, hipStream_t s);

@@ -412,9 +412,23 @@ __global__ void k_pred_init(DevGrid g, DevWork w, int slot, int32_t *list, int64
     if (l < g.n_cells) {
         list[base + l] = (slot << kSlotShift) | int32_t(l);
         w.iters[l] = 0;
+        w.late[l] = 1;
         w.hist[2 * l] = 0;
         w.hist[2 * l + 1] = 0;
     }
+}
+
+__global__ void k_clear_late(DevGrid g, DevWork w) {
+    const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (c < g.n_cells) w.late[c] = 0;
+}
+
+__global__ void k_mark_listed(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list, int count) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int slot, c;
+    decode(list[i], slot, c);
+    tab[slot].w.late[c] = 1;
 }
 
 __global__ void k_set_int(int32_t *p, int v) {
@@ -555,6 +569,27 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
     }
 }
 
+// Sum of p[idx[q] * stride + col] over q in [q0, q1), added in ascending q
+// (the order fixes the rounding); index and value loads are issued kGatherBatch
+// at a time, so a long incidence list costs few dependent round trips.
+constexpr int kGatherBatch = 8;
+__device__ inline double ordered_gather_sum(const double *__restrict__ p, const int32_t *__restrict__ idx, int q0,
+                                            int q1, int stride, int col) {
+    double acc = 0.0;
+    for (int q = q0; q < q1; q += kGatherBatch) {
+        int32_t ix[kGatherBatch];
+#pragma unroll
+        for (int u = 0; u < kGatherBatch; ++u) ix[u] = q + u < q1 ? idx[q + u] : 0;
+        double v[kGatherBatch];
+#pragma unroll
+        for (int u = 0; u < kGatherBatch; ++u) v[u] = q + u < q1 ? p[int64_t(ix[u]) * stride + col] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kGatherBatch; ++u)
+            if (q + u < q1) acc += v[u];
+    }
+    return acc;
+}
+
 // Assembly R[l][col] = sum over the DOF's ascending incidence list of the
 // sub-tet contributions rk (mixed: the FP32 scaled residual D R); work item
 // = (entry, 256 consecutive elements of the cell's DOF-major block).
@@ -574,8 +609,7 @@ __global__ void __launch_bounds__(256) k_round_gather(const DevSlot *__restrict_
         const int64_t t = d0 * nc + e;
         const int64_t l = t / nc;
         const int col = int(t % nc);
-        double acc = 0.0;
-        for (int q = g.inc_ptr[l]; q < g.inc_ptr[l + 1]; ++q) acc += w.rk[int64_t(g.inc_idx[q]) * nc + col];
+        const double acc = ordered_gather_sum(w.rk, g.inc_idx, g.inc_ptr[l], g.inc_ptr[l + 1], nc, col);
         if (g.mixed)
             w.R32[t] = float(acc * g.dscale[l]);
         else
@@ -587,7 +621,7 @@ __global__ void __launch_bounds__(256) k_round_gather(const DevSlot *__restrict_
 // the volume term |J| sum_d V^_d F*bar_d (Sec. 4.4) and the face traces
 // (qbar, Fbar) at the boundary-triangle nodes.
 template <int N, bool VISC>
-__global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevWork w) {
+__global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevWork w, int which) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr int nf = Dim<N>::nf;
     __shared__ double Ks[3 * np * np];
@@ -603,8 +637,8 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
     }
     const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
     const int64_t k = int64_t(blockIdx.x) * spb + s;
-    const bool valid = (s < spb) && (k < g.nsub);
-    const int c = valid ? g.sub_cell[k] : 0;
+    const int c = (s < spb) && (k < g.nsub) ? g.sub_cell[k] : -1;
+    const bool valid = c >= 0 && w.late[c] == which;
     const double dt = *w.dt;
     double G[9], dj = 0.0, mu_c = 0.0;
     double q[5] = {1, 0, 0, 0, 1};
@@ -870,6 +904,8 @@ __device__ inline void ring_state(const DevWork &w, int c, int &k, int &head, bo
 // Tiles of 64 DOFs per cell in the partials buffer of a simulation.
 __device__ inline int part_tiles(const DevGrid &g) { return (g.max_cell_dofs + 63) / 64; }
 
+constexpr int kDotCols = 4;
+
 template <int N>
 __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, int tile, double (*accs)[4]) {
     constexpr int nc = Dim<N>::nc, nt = Dim<N>::nt;
@@ -930,29 +966,29 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
         accs[1][wv] = gmx;
     }
     if (hist_on) {
-        // four history columns per pass, so that their loads are in flight together
-        for (int j0 = 0; j0 <= k; j0 += 4) {
-            double ph[4], pb[4];
+        // kDotCols history columns per pass, so that their loads are in flight together
+        for (int j0 = 0; j0 <= k; j0 += kDotCols) {
+            double ph[kDotCols], pb[kDotCols];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) ph[u] = pb[u] = 0.0;
+            for (int u = 0; u < kDotCols; ++u) ph[u] = pb[u] = 0.0;
 #pragma unroll
             for (int q = 0; q < kPer; ++q) {
                 if (ie[q] < e1) {
-                    double d[4];
+                    double d[kDotCols];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < kDotCols; ++u) {
                         const int j = j0 + u;
                         d[u] = j < k ? dF[int64_t((head + j) % depth) * len + ie[q]] : dfe[q];
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
+                    for (int u = 0; u < kDotCols; ++u) {
                         ph[u] = fma(d[u], dfe[q], ph[u]);
                         pb[u] = fma(d[u], fe[q], pb[u]);
                     }
                 }
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < kDotCols; ++u) {
                 const int j = j0 + u;
                 if (j <= k) {
                     const double sh = wave_sum(ph[u]), sb = wave_sum(pb[u]);
@@ -983,6 +1019,8 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
 // and w.hist[2c + 1] the head slot of the history.  The scaled Cholesky
 // factor is worked on in LDS (Ls, logical rows): loaded with independent
 // loads, updated there, and its changed rows written back.
+constexpr int kSolveBatch = 8;
+
 __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c, int32_t entry, int32_t *next,
                                       int32_t *next_count, double (*Ls)[kMaxDepth]) {
     const int lane = threadIdx.x;
@@ -992,11 +1030,21 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
     const int depth = w.depth;
     const int it = w.iters[c];
     const bool hist_on = depth > 0 && it > 0;
-    // reduce the per-tile partials in tile order
+    // reduce the per-tile partials in tile order (loads batched by kSolveBatch)
     double res = 0.0, gm = 0.0;
-    for (int t = 0; t < ntile; ++t) {
-        res = fmax(res, part[t * kPartStride + 0]);
-        gm = fmax(gm, part[t * kPartStride + 1]);
+    for (int t0 = 0; t0 < ntile; t0 += kSolveBatch) {
+        double a[kSolveBatch], b[kSolveBatch];
+#pragma unroll
+        for (int u = 0; u < kSolveBatch; ++u) {
+            const bool in = t0 + u < ntile;
+            a[u] = in ? part[(t0 + u) * kPartStride + 0] : 0.0;
+            b[u] = in ? part[(t0 + u) * kPartStride + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kSolveBatch; ++u) {
+            res = fmax(res, a[u]);
+            gm = fmax(gm, b[u]);
+        }
     }
     const int it1 = it + 1;
     const bool conv = res <= w.tol * fmax(1.0, gm);
@@ -1043,16 +1091,33 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
             __syncthreads();
         }
     } else {
-        for (int i = 0; i < k; ++i)
-            if (lane <= i) Ls[i][lane] = Lc[i * kMaxDepth + lane];
+        for (int i0 = 0; i0 < k; i0 += kSolveBatch) {
+            double r[kSolveBatch];
+#pragma unroll
+            for (int u = 0; u < kSolveBatch; ++u) r[u] = (i0 + u < k && lane <= i0 + u) ? Lc[(i0 + u) * kMaxDepth + lane] : 0.0;
+#pragma unroll
+            for (int u = 0; u < kSolveBatch; ++u)
+                if (i0 + u < k && lane <= i0 + u) Ls[i0 + u][lane] = r[u];
+        }
         __syncthreads();
     }
     // reduced dots: h_j = <dF_j, dF_new>, b_j = <dF_j, f>, j = 0..k (k = new column)
     double hj = 0.0, bj_raw = 0.0;
     if (lane <= k) {
-        for (int t = 0; t < ntile; ++t) {
-            hj += part[t * kPartStride + 2 + lane];
-            bj_raw += part[t * kPartStride + 2 + kMaxDepth + 1 + lane];
+        for (int t0 = 0; t0 < ntile; t0 += kSolveBatch) {
+            double a[kSolveBatch], b[kSolveBatch];
+#pragma unroll
+            for (int u = 0; u < kSolveBatch; ++u) {
+                const bool in = t0 + u < ntile;
+                a[u] = in ? part[(t0 + u) * kPartStride + 2 + lane] : 0.0;
+                b[u] = in ? part[(t0 + u) * kPartStride + 2 + kMaxDepth + 1 + lane] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < kSolveBatch; ++u)
+                if (t0 + u < ntile) {
+                    hj += a[u];
+                    bj_raw += b[u];
+                }
         }
     }
     const int snew = (head + k) % depth;
@@ -1148,6 +1213,8 @@ __global__ void __launch_bounds__(64) k_round_solve(const DevSlot *__restrict__ 
     }
 }
 
+constexpr int kUpdBatch = 8;
+
 template <int N>
 __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
                                                       const int32_t *__restrict__ count, int tpc) {
@@ -1174,12 +1241,12 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
         for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
             double xv = w.gprev[base + e];
             int j = 0;
-            for (; j + 4 <= kuse; j += 4) {
-                double d[4];
+            for (; j + kUpdBatch <= kuse; j += kUpdBatch) {
+                double d[kUpdBatch];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) d[u] = dG[int64_t((head + j + u) % depth) * len + e];
+                for (int u = 0; u < kUpdBatch; ++u) d[u] = dG[int64_t((head + j + u) % depth) * len + e];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) xv -= gam[j + u] * d[u];
+                for (int u = 0; u < kUpdBatch; ++u) xv -= gam[j + u] * d[u];
             }
             for (; j < kuse; ++j) xv -= gam[j] * dG[int64_t((head + j) % depth) * len + e];
             w.x[base + e] = xv;
@@ -1271,10 +1338,8 @@ __global__ void __launch_bounds__(256) k_rhs(DevGrid g, DevWork w) {
     if (t >= g.ndof * 5) return;
     const int64_t l = t / 5;
     const int v = int(t % 5);
-    double acc = 0.0;
-    for (int e = g.inc_ptr[l]; e < g.inc_ptr[l + 1]; ++e) acc += w.vk[int64_t(g.inc_idx[e]) * 5 + v];
-    double fac = 0.0;
-    for (int e = g.finc_ptr[l]; e < g.finc_ptr[l + 1]; ++e) fac += w.fc[int64_t(g.finc_idx[e]) * 5 + v];
+    const double acc = ordered_gather_sum(w.vk, g.inc_idx, g.inc_ptr[l], g.inc_ptr[l + 1], 5, v);
+    const double fac = ordered_gather_sum(w.fc, g.finc_idx, g.finc_ptr[l], g.finc_ptr[l + 1], 5, v);
     w.rhs[t] = acc - fac;
 }
 
@@ -1454,15 +1519,27 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
     });
 }
 
-hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, hipStream_t s) {
+hipError_t launch_clear_late(const DevGrid &g, const DevWork &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_late, dim3(blocks_for(g.n_cells, 256)), dim3(256), 0, s, g, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_listed(const DevSlot *tab, const int32_t *list, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mark_listed, dim3(blocks_for(count, 256)), dim3(256), 0, s, tab, list, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, int which, hipStream_t s) {
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
         if (g.mu != 0.0 || g.av)
-            hipLaunchKernelGGL((k_subtet_post<NN, true>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w);
+            hipLaunchKernelGGL((k_subtet_post<NN, true>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w,
+                               which);
         else
             hipLaunchKernelGGL((k_subtet_post<NN, false>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g,
-                               w);
+                               w, which);
         return hipGetLastError();
     });
 }
