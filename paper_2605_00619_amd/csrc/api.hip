@@ -658,6 +658,16 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         ref.zsum[j] = sacc;
         ref.fn[j] = R.face_nodes[j];
     }
+    {
+        const int inner = 3 * R.np, steps = (inner + 3) / 4, tiles = (R.np + 15) / 16;
+        for (int t = 0; t < tiles; ++t)
+            for (int j = 0; j < steps; ++j)
+                for (int l = 0; l < 64; ++l) {
+                    const int row = 16 * t + l % 16, kk = 4 * j + l / 16;
+                    ref.Kfrag[(t * steps + j) * 64 + l] =
+                        row < R.np && kk < inner ? R.K[((kk / R.np) * R.np + row) * R.np + kk % R.np] : 0.0;
+                }
+    }
     for (int a = 0; a < R.nt; ++a) ref.w[a] = R.w[a];
     for (int i = 0; i < R.nt * R.nt; ++i) {
         ref.Ktau_inv[i] = R.Ktau_inv[i];

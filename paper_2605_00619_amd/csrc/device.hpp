@@ -17,6 +17,12 @@ struct DevRef {
     double Ktau_inv[16];     // inverse of the upwind time operator
     double Ktau[16];         // upwind time operator psi_a(1) psi_b(1) - int psi_a' psi_b
     int fn[10];              // face node -> reference node
+    // K^ as the A operand of the sub-tet contraction on the matrix cores:
+    // tile (row tile t, k-step j) of the 16 x 4 blocks of A[m][d np + p] =
+    // K^_d[m][p], zero-padded, one double per lane of v_mfma_f64_16x16x4f64
+    // (A[i][k] in lane i + 16 k), at (t * steps + j) * 64 + lane with
+    // steps = (3 np + 3) / 4
+    double Kfrag[2 * 15 * 64];
 };
 
 struct DevGrid {

@@ -466,30 +466,60 @@ __device__ inline void node_flux(const double *Dt, const double (*qn)[5], int m,
             fstar[d * 5 + v] = dt * (G[d * 3 + 0] * F[0][v] + G[d * 3 + 1] * F[1][v] + G[d * 3 + 2] * F[2][v]);
 }
 
-// Work item = (entry, chunk of spb sub-tets of the cell).  Per sub-tet and
-// time node: nodal flux and the reference stiffness contraction
-// rk[a][m] = w_a |J| sum_d sum_p K^_d[m][p] f*_d[a][p] (eq:ader4); in mixed
-// precision the sub-tet's part of (K_tau (x) M_i)(q - 1 (x) u^n) is added,
-// which makes rk the unpreconditioned residual of eq:ADER-localCauchy.
-// Block 0 clears the next list's length.  VISC: some simulation of the group
-// has a physical or artificial viscosity; MIXED: the group's precision.
+// Operand layout of v_mfma_f64_16x16x4f64 (D = A B + C, A 16x4, B 4x16, D
+// 16x16, one double of A and of B and four of D per lane): A[i][k] in lane
+// i + 16 k (the host writes DevRef::Kfrag in this order), B[k][j] in lane
+// j + 16 k, D[i][j] in lane j + 16 (i % 4), item i / 4.
+__device__ inline int mf_b_k(int l) { return l / 16; }
+__device__ inline int mf_b_col(int l) { return l % 16; }
+__device__ inline int mf_d_row(int l, int r) { return l / 16 + 4 * r; }
+__device__ inline int mf_d_col(int l, int) { return l % 16; }
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Shape of the chunk's stiffness contraction as one matrix product:
+// rows = node m, inner index = (d, p), columns = (sub-tet, time node, variable).
+template <int N>
+struct Contraction {
+    static constexpr int np = Dim<N>::np;
+    static constexpr int inner = 3 * np;
+    static constexpr int ks = (inner + 3) / 4;  // k-steps of 4
+    static constexpr int cols = Dim<N>::spb * Dim<N>::nt * 5;
+    static constexpr int ct = (cols + 15) / 16;  // column tiles
+    static constexpr int mt = (np + 15) / 16;    // row tiles
+    static constexpr int ld = 16 * ct;           // row stride of the B operand in LDS
+};
+
+// Work item = (entry, chunk of spb sub-tets of the cell), 256 threads.  Per
+// sub-tet and time node (one thread each): the nodal flux f*; then the
+// reference stiffness contraction rk[a][m] = w_a |J| sum_d sum_p K^_d[m][p]
+// f*_d[a][p] (eq:ader4) of the whole chunk as one product on the matrix
+// cores, K^ (rows m, inner (d, p)) times f* (inner (d, p), columns (sub-tet,
+// a, v)), wave w taking column tiles w, w + 4, ...  In mixed precision the
+// sub-tet's part of (K_tau (x) M_i)(q - 1 (x) u^n) is added, which makes rk
+// the unpreconditioned residual of eq:ADER-localCauchy.  Block 0 clears the
+// next list's length.  VISC: some simulation of the group has a physical or
+// artificial viscosity; MIXED: the group's precision.
 template <int N, bool VISC, bool MIXED>
-__global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_per_eu(2))) k_round_subtet(const DevSlot *__restrict__ tab,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_round_subtet(const DevSlot *__restrict__ tab,
                                                                    const int32_t *__restrict__ list,
                                                                    const int32_t *__restrict__ count, int chunks,
                                                                    int32_t *next_count) {
+    using C = Contraction<N>;
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
+    constexpr bool QS = VISC || MIXED;  // nodal states shared through LDS
     constexpr int nd = VISC ? 3 * np * np : 1, nm = MIXED ? np * np : 1, sm = MIXED ? spb : 1;
-    __shared__ double Kt[3 * np * np];  // reference matrices transposed: (d, m, p) at (d np + p) np + m
-    __shared__ double Dt[nd];
+    constexpr int qsp = QS ? spb : 1, qnt = QS ? nt : 1, qnp = QS ? np : 1;
+    constexpr int mnp = MIXED ? np : 1;
+    __shared__ double fT[4 * C::ks][C::ld];          // B operand: f*_d[s][a][p][v] at (d np + p, (s nt + a) 5 + v)
+    __shared__ double Dt[nd];                        // D^ transposed, as node_flux reads it
     __shared__ double Mt[nm];
-    __shared__ double qs[spb][nt][np][5];
-    __shared__ double fs[spb][nt][np][15];
-    __shared__ double us[sm][np][5];
-    __shared__ double mt[sm][nt][np][5];  // M^ (q_b - u^n) per time node
+    __shared__ double qs[qsp][qnt][qnp][5];  // nodal states; in mixed precision then M^ (q_b - u^n)
+    __shared__ double us[sm][mnp][5];
+    __shared__ double djs[spb];
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
+    const bool node = s < spb;
     const int n_items = *count * chunks;
     bool loaded = false;
     for (int item = xcd_block(); item < n_items; item += gridDim.x) {
@@ -502,17 +532,21 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
         const int chunk = item % chunks;
         if (chunk >= nchunk) continue;
         if (!loaded) {
+            // the same for every item of the block: the padding of the
+            // operands stays zero, the inner index beyond 3 np included
+            for (int t = tid; t < 4 * C::ks * C::ld; t += blockDim.x) fT[t / C::ld][t % C::ld] = 0.0;
             if (MIXED)
                 for (int t = tid; t < np * np; t += blockDim.x) Mt[MIXED ? (t % np) * np + t / np : 0] = g.ref->M[t];
-            for (int t = tid; t < 3 * np * np; t += blockDim.x) {
-                const int d = t / (np * np), mm = (t / np) % np, p = t % np;
-                Kt[(d * np + p) * np + mm] = g.ref->K[t];
-                if (VISC) Dt[VISC ? (d * np + p) * np + mm : 0] = g.ref->D[t];
-            }
+            if (VISC)
+                for (int t = tid; t < 3 * np * np; t += blockDim.x) {
+                    const int d = t / (np * np), mm = (t / np) % np, p = t % np;
+                    Dt[VISC ? (d * np + p) * np + mm : 0] = g.ref->D[t];
+                }
             loaded = true;
+            __syncthreads();
         }
         const int64_t k = s0 + int64_t(chunk) * spb + s;
-        const bool valid = (s < spb) && (k < s1);
+        const bool valid = node && (k < s1);
         const double dt = *w.dt;
         double G[9], dj = 0.0, mu_c = 0.0;
         double q[5] = {1, 0, 0, 0, 1};
@@ -521,49 +555,68 @@ __global__ void __launch_bounds__(Dim<N>::threads) __attribute__((amdgpu_waves_p
             dj = g.geo[k * 10 + 9];
             mu_c = w.mu_cell[c];
             const int64_t l = g.dof_ptr[c] + g.conn[k * np + m];
-            for (int v = 0; v < 5; ++v) {
-                q[v] = w.x[l * nc + a * 5 + v];
-                qs[s][a][m][v] = q[v];
-            }
+            for (int v = 0; v < 5; ++v) q[v] = w.x[l * nc + a * 5 + v];
+            if (QS)
+                for (int v = 0; v < 5; ++v) qs[QS ? s : 0][QS ? a : 0][QS ? m : 0][v] = q[v];
             if (MIXED && a == 0)
-                for (int v = 0; v < 5; ++v) us[MIXED ? s : 0][m][v] = w.u[v * g.ndof + l];
+                for (int v = 0; v < 5; ++v) us[MIXED ? s : 0][MIXED ? m : 0][v] = w.u[v * g.ndof + l];
+            if (a == 0 && m == 0) djs[s] = dj;
         }
-        __syncthreads();
+        if (QS) __syncthreads();
         if (valid) {
-            double F[3][5];
-            node_flux<N, VISC>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
+            double F[3][5], fst[15];
+            node_flux<N, VISC>(Dt, qs[QS ? s : 0][QS ? a : 0], m, G, q, g.gamma, mu_c, dt, fst, F);
+            for (int d = 0; d < 3; ++d)
+                for (int v = 0; v < 5; ++v) fT[d * np + m][(s * nt + a) * 5 + v] = fst[d * 5 + v];
         }
         if (MIXED) {
             __syncthreads();
-            // thread (s, b = a, m): the sub-tet mass product of time node b
+            // thread (s, b = a, m): the sub-tet mass product of time node b,
+            // stored over the nodal states once every thread has read them
             double t[5] = {0, 0, 0, 0, 0};
             if (valid)
                 for (int p = 0; p < np; ++p) {
                     const double mm = Mt[MIXED ? p * np + m : 0];
-                    for (int v = 0; v < 5; ++v) t[v] += mm * (qs[s][a][p][v] - us[MIXED ? s : 0][p][v]);
+                    for (int v = 0; v < 5; ++v)
+                        t[v] += mm * (qs[QS ? s : 0][QS ? a : 0][QS ? p : 0][v] - us[MIXED ? s : 0][MIXED ? p : 0][v]);
                 }
-            for (int v = 0; v < 5; ++v) mt[MIXED ? s : 0][a][m][v] = valid ? t[v] : 0.0;
+            __syncthreads();
+            if (node)
+                for (int v = 0; v < 5; ++v) qs[QS ? s : 0][QS ? a : 0][QS ? m : 0][v] = valid ? t[v] : 0.0;
         }
         __syncthreads();
-        if (valid) {
-            double r[5] = {0, 0, 0, 0, 0};
-            for (int d = 0; d < 3; ++d)
-                for (int p = 0; p < np; ++p) {
-                    const double kk = Kt[(d * np + p) * np + m];
-                    for (int v = 0; v < 5; ++v) r[v] += kk * fs[s][a][p][d * 5 + v];
-                }
-            const double sc = g.ref->w[a] * dj;
-            double *out = w.rk + (k * np + m) * nc + a * 5;
-            if (MIXED) {
-                double mr[5] = {0, 0, 0, 0, 0};
-                for (int b = 0; b < nt; ++b) {
-                    const double kt = g.ref->Ktau[a * nt + b];
-                    for (int v = 0; v < 5; ++v) mr[v] += kt * mt[MIXED ? s : 0][b][m][v];
-                }
-                for (int v = 0; v < 5; ++v) out[v] = sc * r[v] + dj * mr[v];
-            } else {
-                for (int v = 0; v < 5; ++v) out[v] = sc * r[v];
+        const gptr<double> Kf = (gptr<double>)uni_ptr(g.ref->Kfrag) + lane;
+        for (int ctile = wv; ctile < C::ct; ctile += 4) {
+            dbl4 acc[C::mt];
+#pragma unroll
+            for (int mtile = 0; mtile < C::mt; ++mtile) acc[mtile] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kst = 0; kst < C::ks; ++kst) {
+                const double bv = fT[4 * kst + mf_b_k(lane)][16 * ctile + mf_b_col(lane)];
+#pragma unroll
+                for (int mtile = 0; mtile < C::mt; ++mtile)
+                    acc[mtile] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kf[(mtile * C::ks + kst) * kWave], bv, acc[mtile], 0,
+                                                                      0, 0);
             }
+#pragma unroll
+            for (int mtile = 0; mtile < C::mt; ++mtile)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * mtile + mf_d_row(lane, r), col = 16 * ctile + mf_d_col(lane, r);
+                    if (row >= np || col >= C::cols) continue;
+                    const int ss = col / (nt * 5), aa = (col / 5) % nt, vv = col % 5;
+                    const int64_t kk = s0 + int64_t(chunk) * spb + ss;
+                    if (kk >= s1) continue;
+                    const double djv = djs[ss];
+                    double val = g.ref->w[aa] * djv * acc[mtile][r];
+                    if (MIXED) {
+                        double mr = 0.0;
+                        for (int b = 0; b < nt; ++b)
+                            mr += g.ref->Ktau[aa * nt + b] * qs[QS ? ss : 0][QS ? b : 0][QS ? row : 0][vv];
+                        val += djv * mr;
+                    }
+                    w.rk[(kk * np + row) * nc + aa * 5 + vv] = val;
+                }
         }
         __syncthreads();  // LDS is rewritten by the next item
     }
@@ -1498,7 +1551,7 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
         const int per = int((int64_t(a.max_cell_dofs) * D::nc + 255) / 256);
         auto sub = a.visc ? (a.mixed ? k_round_subtet<NN, true, true> : k_round_subtet<NN, true, false>)
                           : (a.mixed ? k_round_subtet<NN, false, true> : k_round_subtet<NN, false, false>);
-        hipLaunchKernelGGL(sub, grid(a.shape.g_sub, chunks), dim3(D::threads), 0, s, a.tab, a.list, a.count, chunks,
+        hipLaunchKernelGGL(sub, grid(a.shape.g_sub, chunks), dim3(256), 0, s, a.tab, a.list, a.count, chunks,
                            a.next_count);
         hipLaunchKernelGGL(k_round_gather<NN>, grid(a.shape.g_gather, per), dim3(256), 0, s, a.tab, a.list, a.count,
                            per);
@@ -1578,7 +1631,7 @@ IterShape resident_shape(int N, int mixed, int visc) {
                                      : reinterpret_cast<const void *>(&k_round_subtet<NN, true, false>))
                             : (mixed ? reinterpret_cast<const void *>(&k_round_subtet<NN, false, true>)
                                      : reinterpret_cast<const void *>(&k_round_subtet<NN, false, false>)),
-                       D::threads);
+                       256);
         sh.g_gather = fit(reinterpret_cast<const void *>(&k_round_gather<NN>), 256);
         sh.g_minv = mixed ? fit(reinterpret_cast<const void *>(&k_round_minv32<D::nc>), 256)
                           : fit(reinterpret_cast<const void *>(&k_round_minv<D::nc>), 256);
