@@ -214,7 +214,8 @@ def serving_run(log) -> dict:
     return out
 
 
-def run_workload(args, key: str, precision: str, log, start=None, keep_initial: bool = False) -> dict:
+def run_workload(args, key: str, precision: str, log, start=None, keep_initial: bool = False,
+                 guess: bool = True) -> dict:
     """Build the workload, autotune the launch shape, run the warm-up and the
     timed steps with the M^-1 kernel's HIP events and byte counter."""
     import numpy as np
@@ -231,7 +232,8 @@ def run_workload(args, key: str, precision: str, log, start=None, keep_initial: 
     log(f"[{key} {precision}] mesh: {mesh['n_cells']} cells in {time.time() - t0:.1f}s")
     t0 = time.time()
     params = afe.Params(accel_depth=args.depth, max_iter=args.max_iter, tol=args.tol,
-                        precision=afe.AFE_MIXED if precision == "mixed" else afe.AFE_FP64)
+                        precision=afe.AFE_MIXED if precision == "mixed" else afe.AFE_FP64,
+                        predictor_guess=guess and not args.no_guess)
     cd = afe.CellData(mesh, wl["N"], params)
     torch.cuda.synchronize()
     log(f"[{key} {precision}] cell data: ndof={cd.ndof} subtets={cd.n_subtets} max_cell_dofs={cd.max_cell_dofs} "
@@ -316,6 +318,8 @@ def main() -> int:
     ap.add_argument("--no-serve", action="store_true", help="skip the serving session")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving session")
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner's")
+    ap.add_argument("--no-guess", action="store_true",
+                    help="start every predictor iteration from u^n (default: from the previous step's predictor)")
     ap.add_argument("--no-legs", dest="legs", action="store_false",
                     help="skip the mixed-precision and mesh-variant legs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -368,6 +372,8 @@ def main() -> int:
             "subtets": r["subtets"], "N": wl["N"], "cfl": args.cfl, "dt_last": r["dt"],
             "predictor_iters_mean": r["iters_mean"], "predictor_iters_max": r["iters_max"],
             "anderson_depth": args.depth, "tol": args.tol, "launch_shape": r["shape"],
+            "predictor_start": "u^n" if args.no_guess else
+                               "previous step's predictor extrapolated in time (u^n on the first step)",
         },
         "copy_probe_bytes": copy_bytes,
         "roofline": r["roofline"],
@@ -385,6 +391,13 @@ def main() -> int:
         out["mesh_variant"] = {k: q[k] for k in ("value", "ms_per_step", "iters_mean", "iters_max", "ndof")}
         out["mesh_variant"]["workload"] = WORKLOADS["wave16_p3_q"]["desc"] if args.workload == "wave16_p3" else ""
         del q
+        if not args.no_guess:
+            # the same workload with every predictor iteration started from u^n
+            p = run_workload(args, args.workload, "fp64", log, start=main_run["u_start"], guess=False)
+            out["start_from_un"] = {k: p[k] for k in ("value", "ms_per_step", "iters_mean", "iters_max")}
+            out["start_from_un"]["rel_linf_vs_main_final_state"] = float(
+                (p["u_end"] - main_run["u_end"]).abs().max() / main_run["u_end"].abs().max())
+            del p
     u0_np = main_run["u_initial"].cpu().numpy() if main_run.get("u_initial") is not None else None
     mesh, dt = main_run["mesh"], main_run["dt"]
     del main_run, r

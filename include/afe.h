@@ -79,6 +79,13 @@ typedef struct {
                          /* Jacobi-scaled copy of M_i^{-1} as preconditioner of the   */
                          /* FP64 residual of eq:ADER-localCauchy (same fixed point)   */
     size_t hbm_budget;   /* bytes of device memory the object may use (0 = no cap)  */
+    int32_t predictor_guess; /* 0: every step starts the predictor iteration from    */
+                         /* q = u^n at all time nodes; 1: from the previous step's    */
+                         /* converged predictor of this object extrapolated in time   */
+                         /* (Lagrange on the time nodes, shifted to u^n), when that   */
+                         /* step succeeded on the same state and the cell is not      */
+                         /* troubled.  The fixed point, hence the result up to the    */
+                         /* stop test, is the same; fewer iterations are needed.      */
 } afe_params;
 
 typedef struct {

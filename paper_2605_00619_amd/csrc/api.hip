@@ -203,6 +203,7 @@ size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub
 
 afe_status check_params(const afe_params *p) {
     if (p->precision != AFE_FP64 && p->precision != AFE_MIXED) return fail(AFE_E_ARG, "unknown precision");
+    if (p->predictor_guess != 0 && p->predictor_guess != 1) return fail(AFE_E_ARG, "predictor_guess must be 0 or 1");
     if (p->accel_depth < 0 || p->accel_depth > 63) return fail(AFE_E_ARG, "accel_depth must be in [0, 63]");
     if (p->max_iter < 1) return fail(AFE_E_ARG, "max_iter must be >= 1");
     if (!(p->gamma > 1.0) || p->mu < 0.0 || !(p->tol >= 0.0))
@@ -294,6 +295,8 @@ afe_status launch_pre(Engine &E, bool cfl_dt, hipStream_t s) {
             HIP_TRY(afe::launch_detect(cd->g, w, E.u[sl], s));
             if (cfl_dt) HIP_TRY(afe::launch_cfl_dt(cd->g, w, E.cfl[sl], cd->host.h_min, cd->d_scalar, s));
             HIP_TRY(afe::launch_pred_init(cd->g, w, sl, gr.lists, gr.base[i], s));
+            // the start is consumed: only a completed step (k_step_stats) re-arms it
+            HIP_TRY(afe::launch_set_count(w.guess_ok, 0, s));
         }
         HIP_TRY(afe::launch_set_count(gr.counts, int(gr.cells), s));
     }
@@ -614,6 +617,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     g.m1 = params->m1;
     g.av = params->av;
     g.mixed = params->precision == AFE_MIXED ? 1 : 0;
+    g.guess = params->predictor_guess;
     std::vector<int64_t> minv_ptr(h.n_cells + 1, 0), minv32_ptr(h.n_cells + 1, 0);
     for (int c = 0; c < h.n_cells; ++c) {
         int64_t n = h.dof_ptr[c + 1] - h.dof_ptr[c];
@@ -668,7 +672,10 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
                         row < R.np && kk < inner ? R.K[((kk / R.np) * R.np + row) * R.np + kk % R.np] : 0.0;
                 }
     }
-    for (int a = 0; a < R.nt; ++a) ref.w[a] = R.w[a];
+    for (int a = 0; a < R.nt; ++a) {
+        ref.w[a] = R.w[a];
+        ref.tau[a] = R.tau[a];
+    }
     for (int i = 0; i < R.nt * R.nt; ++i) {
         ref.Ktau_inv[i] = R.Ktau_inv[i];
         ref.Ktau[i] = R.Ktau[i];
@@ -710,7 +717,8 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(w.gamma, size_t(h.n_cells) * 63)) != hipSuccess ||
         (e = cd->alloc(w.kuse, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.late, size_t(h.n_cells))) != hipSuccess ||
-        (e = cd->alloc(w.dt, 1)) != hipSuccess ||
+        (e = cd->alloc(w.dt, 1)) != hipSuccess || (e = cd->alloc(w.dt_prev, 1)) != hipSuccess ||
+        (e = cd->alloc(w.guess_ok, 1)) != hipSuccess || (e = hipMemsetAsync(w.guess_ok, 0, sizeof(int32_t), s)) != hipSuccess ||
         (e = cd->alloc(w.status, kStatusWords)) != hipSuccess || (e = cd->alloc(cd->d_scalar, 1)) != hipSuccess ||
         (e = hipHostMalloc(&cd->h_status, kStatusWords * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
         (e = hipHostMalloc(&cd->h_scalar, 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess) {
@@ -862,6 +870,7 @@ afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *str
     if (E.u[0] != u) {
         E.u[0] = const_cast<double *>(u);
         E.dirty = true;
+        HIP_TRY(afe::launch_set_count(cd->w.guess_ok, 0, s));  // another state: start from u^n
     }
     AFE_TRY(sync_layout(E, s));
     apply_shape(E);
@@ -952,6 +961,7 @@ afe_status afe_batch_attach(afe_batch *b, afe_cell_data *cd, double *u, double c
     int sl = 0;
     while (sl < afe::kMaxSlots && E.cds[sl]) ++sl;
     if (sl == afe::kMaxSlots) return fail(AFE_E_ARG, "batch full");
+    HIP_TRY(hipMemset(cd->w.guess_ok, 0, sizeof(int32_t)));  // the batch's state may be another one
     E.cds[sl] = cd;
     E.u[sl] = u;
     E.cfl[sl] = cfl;
@@ -1041,9 +1051,11 @@ afe_status afe_batch_tune(afe_batch *b, void *stream, afe_launch_shape *chosen) 
             E.drop_graphs();
             for (int rep = 0; rep < 2; ++rep) {  // the first run captures graphs and warms caches
                 for (int sl = 0; sl < afe::kMaxSlots; ++sl)
-                    if (E.cds[sl])
+                    if (E.cds[sl]) {
                         HIP_TRY(hipMemcpyAsync(work[sl], saved[sl], size_t(5) * E.cds[sl]->host.ndof * sizeof(double),
                                                hipMemcpyDeviceToDevice, s));
+                        HIP_TRY(afe::launch_set_count(E.cds[sl]->w.guess_ok, 0, s));  // every trial starts from u^n
+                    }
                 AFE_TRY(sync_layout(E, s));
                 HIP_TRY(hipStreamSynchronize(s));
                 const auto t0 = std::chrono::steady_clock::now();
@@ -1094,7 +1106,12 @@ afe_status afe_batch_tune(afe_batch *b, void *stream, afe_launch_shape *chosen) 
                     c.graph = gflag;
                     st = trial(c);
                 }
-        for (int sl = 0; sl < afe::kMaxSlots; ++sl) E.u[sl] = orig[sl];
+        for (int sl = 0; sl < afe::kMaxSlots; ++sl) {
+            E.u[sl] = orig[sl];
+            // the predictors left by the trials belong to the working copies
+            if (E.cds[sl] && afe::launch_set_count(E.cds[sl]->w.guess_ok, 0, s) != hipSuccess && st == AFE_OK)
+                st = fail(AFE_E_HIP, "predictor start reset");
+        }
         E.dirty = true;
         E.shape = best;
         E.drop_graphs();

@@ -14,6 +14,7 @@ struct DevRef {
     double Z[10 * 10];       // face mass on the reference triangle
     double zsum[10];         // int_tri phi_j = sum_i Z[i][j]
     double w[4];             // Gauss-Legendre weights on [0, 1]
+    double tau[4];           // Gauss-Legendre nodes on [0, 1]
     double Ktau_inv[16];     // inverse of the upwind time operator
     double Ktau[16];         // upwind time operator psi_a(1) psi_b(1) - int psi_a' psi_b
     int fn[10];              // face node -> reference node
@@ -33,6 +34,7 @@ struct DevGrid {
     double gamma, mu, m1;
     int av;
     int mixed;                // 1: FP32 preconditioner for the predictor iteration
+    int guess;                // 1: predictor start extrapolated from the previous step
     // connectivity and geometry
     const int64_t *dof_ptr;   // [n_cells + 1]
     const int64_t *sub_ptr;   // [n_cells + 1]
@@ -82,6 +84,8 @@ struct DevWork {
     int32_t *kuse;   // [n_cells] history columns used by the update
     int32_t *late;   // [n_cells] 1: time integrals left to the final pass (still iterating at the early pass)
     double *dt;      // [1] time step of the current step
+    double *dt_prev; // [1] time step of the last successful step
+    int32_t *guess_ok; // [1] 1: x holds the converged predictor of that step
     const double *u; // state u^n of the current step, SoA [5][ndof] (caller-owned)
     double tol;      // predictor stop: max|G(q)-q| <= tol * max(1, max|G(q)|)
     int max_iter;

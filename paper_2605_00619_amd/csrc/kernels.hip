@@ -402,13 +402,56 @@ __device__ inline void decode(int32_t e, int &slot, int &c) {
     c = e & (kMaxCellsPerSlot - 1);
 }
 
+// Lagrange basis on the nt time nodes at t.
+template <int NT>
+__device__ inline void time_lagrange(const double *tau, double t, double L[NT]) {
+    for (int a = 0; a < NT; ++a) {
+        double v = 1.0;
+        for (int c = 0; c < NT; ++c)
+            if (c != a) v *= (t - tau[c]) / (tau[a] - tau[c]);
+        L[a] = v;
+    }
+}
+
+// Start of the predictor iteration.  From u^n: one thread per element of the
+// DOF-major iterate (consecutive threads write consecutive elements).  From
+// the previous step's converged predictor q' (still in x): one thread per
+// (DOF, variable), q(tau_b) = u^n + sum_a (L_a(1 + r tau_b) - L_a(1)) q'(tau_a)
+// with r = dt / dt', the polynomial continued past the old step and shifted
+// to the new initial data; cells with a troubled flag start from u^n.  The
+// first n_cells threads also reset the cell's counters and list entry.
 template <int N>
 __global__ void k_pred_init(DevGrid g, DevWork w, int slot, int32_t *list, int64_t base) {
     constexpr int nc = Dim<N>::nc, nt = Dim<N>::nt;
-    const int64_t l = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (l < g.ndof)
-        for (int a = 0; a < nt; ++a)
-            for (int v = 0; v < 5; ++v) w.x[l * nc + a * 5 + v] = w.u[v * g.ndof + l];
+    const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const bool guess = g.guess && *w.guess_ok != 0;
+    if (!guess) {
+        if (t < g.ndof * nc) {
+            const int64_t l = t / nc;
+            w.x[t] = w.u[(t % nc) % 5 * g.ndof + l];
+        }
+    } else if (t < g.ndof * 5) {
+        const int64_t l = t / 5;
+        const int v = int(t % 5);
+        const double un = w.u[v * g.ndof + l];
+        double *xl = w.x + l * nc + v;
+        if (w.beta[g.dof_cell[l]] > 0.0) {
+            for (int b = 0; b < nt; ++b) xl[b * 5] = un;
+        } else {
+            const double r = *w.dt / *w.dt_prev;
+            double L1[nt], qp[nt];
+            time_lagrange<nt>(g.ref->tau, 1.0, L1);
+            for (int a = 0; a < nt; ++a) qp[a] = xl[a * 5];
+            for (int b = 0; b < nt; ++b) {
+                double Lb[nt];
+                time_lagrange<nt>(g.ref->tau, 1.0 + r * g.ref->tau[b], Lb);
+                double acc = un;
+                for (int a = 0; a < nt; ++a) acc += (Lb[a] - L1[a]) * qp[a];
+                xl[b * 5] = acc;
+            }
+        }
+    }
+    const int64_t l = t;
     if (l < g.n_cells) {
         list[base + l] = (slot << kSlotShift) | int32_t(l);
         w.iters[l] = 0;
@@ -1412,6 +1455,11 @@ __global__ void k_reset_status(DevWork w, int n_cells) {
 // Predictor iteration counts over the cells of one simulation: status[4] =
 // min, status[5] = max, status[6..7] = 64-bit sum.
 __global__ void __launch_bounds__(1024) k_step_stats(DevWork w, int n_cells) {
+    if (threadIdx.x == 0) {
+        // a successful step leaves its converged predictor in x for the next start
+        *w.guess_ok = w.status[0] == 0 ? 1 : 0;
+        *w.dt_prev = *w.dt;
+    }
     __shared__ int smin[16], smax[16];
     __shared__ unsigned long long ssum[16];
     int mn = INT_MAX, mx = 0;
@@ -1523,7 +1571,8 @@ hipError_t launch_set_dt(const DevWork &w, double dt, hipStream_t s) {
 
 hipError_t launch_pred_init(const DevGrid &g, const DevWork &w, int slot, int32_t *list, int64_t base, hipStream_t s) {
     return dispatch(g.N, [&](auto n) {
-        int64_t m = g.ndof > g.n_cells ? g.ndof : g.n_cells;
+        const int64_t elems = g.ndof * Dim<decltype(n)::value>::nc;
+        const int64_t m = elems > g.n_cells ? elems : g.n_cells;
         hipLaunchKernelGGL(k_pred_init<decltype(n)::value>, dim3(blocks_for(m, 256)), dim3(256), 0, s, g, w, slot,
                            list, base);
         return hipGetLastError();
