@@ -43,10 +43,21 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the dominant kernels' own source text (the M^-1 tile routine and
+    the FP64 and FP32 predictor launches): counters taken on them stay valid
+    across unrelated edits, and become stale when these change."""
+    with open(os.path.join(ROOT, "paper_2605_00619_amd", "csrc", "kernels.hip")) as fh:
+        src = fh.read()
     h = hashlib.sha256()
-    for f in ("kernels.hip", "api.hip", "device.hpp"):
-        with open(os.path.join(ROOT, "paper_2605_00619_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    for sig in ("__device__ inline void minv_tile(", "k_round_minv(", "k_round_minv32("):
+        i = src.index(sig)
+        j = src.index("{", i)
+        depth = 0
+        for k in range(j, len(src)):
+            depth += {"{": 1, "}": -1}.get(src[k], 0)
+            if depth == 0:
+                break
+        h.update(src[i:k + 1].encode())
     return h.hexdigest()[:16]
 
 
