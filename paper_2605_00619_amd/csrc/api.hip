@@ -78,6 +78,9 @@ struct Engine {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_early = nullptr;
     bool forked = false;
+    // early corrector: the caller steps u in full (not a predictor-only call)
+    bool allow_correct = false;
+    bool forked2 = false;
     hipGraphExec_t g_pre = nullptr, g_post = nullptr, g_chunk[2] = {nullptr, nullptr};
     // profiling of the first group's M^{-1} launches
     bool prof_on = false;
@@ -196,7 +199,7 @@ size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub
     b += size_t(nsub) * nf * 25 * sizeof(double) + size_t(nsub) * np * 5 * sizeof(double);  // traces, faces, volume
     b += ndof * (5 * 8 + 8 + 4 + 8 + 4 + 4);  // rhs, column sums, DOF cell, scales, incidence offsets
     b += size_t(nsub) * (2 * np * 4 + 10 * 8 + 4 * 8 + 4 + 4 + 2 * nf * 4);  // connectivity, geometry, incidences
-    b += n_cells * ((2 * 63 * 63 + 2 * 63) * 8 + 92);  // Gram / Cholesky, coefficients, per-cell scalars and offsets
+    b += n_cells * ((2 * 63 * 63 + 2 * 63) * 8 + 96);  // Gram / Cholesky, coefficients, per-cell scalars and offsets
     b += 2 * n_cells * sizeof(int32_t);           // predictor list of a batch of one
     return b;
 }
@@ -375,7 +378,7 @@ afe_status launch_early_post(Engine &E, int it, const std::vector<int> &upper, h
         for (int sl : gr.slots) HIP_TRY(afe::launch_clear_late(E.cds[sl]->g, E.tab[sl].w, s));
     for (size_t gi = 0; gi < E.groups.size(); ++gi) {
         const Group &gr = E.groups[gi];
-        HIP_TRY(afe::launch_mark_listed(E.d_tab, gr.lists + size_t(it % 2) * gr.cells, upper[gi], s));
+        HIP_TRY(afe::launch_mark_listed(E.d_tab, gr.lists + size_t(it % 2) * gr.cells, upper[gi], 2, s));
     }
     HIP_TRY(hipEventRecord(E.ev_fork, s));
     HIP_TRY(hipStreamWaitEvent(E.side, E.ev_fork, 0));
@@ -383,6 +386,40 @@ afe_status launch_early_post(Engine &E, int it, const std::vector<int> &upper, h
         for (int sl : gr.slots) HIP_TRY(afe::launch_pred_post(E.cds[sl]->g, E.tab[sl].w, 0, E.side));
     HIP_TRY(hipEventRecord(E.ev_early, E.side));
     E.forked = true;
+    return AFE_OK;
+}
+
+// Later, when at most 1/kLateCorrectFraction of the cells still iterate: the
+// time integrals of the cells that converged since the early pass (middle
+// pass), then the corrector of every cell neither listed nor next to a listed
+// cell, whose own and neighbours' time integrals are then all final, on the
+// side stream after the early pass.  The final pass corrects the rest.  The
+// predictor kernels read u^n of listed cells only, which this pass leaves
+// alone; the pass a cell falls in does not change its bits.
+constexpr int64_t kLateCorrectFraction = 256;
+
+afe_status launch_early_correct(Engine &E, int it, const std::vector<int> &upper, hipStream_t s) {
+    for (auto &gr : E.groups)
+        for (int sl : gr.slots) {
+            HIP_TRY(afe::launch_relabel_late(E.cds[sl]->g, E.tab[sl].w, s));
+            HIP_TRY(afe::launch_clear_late2(E.cds[sl]->g, E.tab[sl].w, s));
+        }
+    for (size_t gi = 0; gi < E.groups.size(); ++gi) {
+        const Group &gr = E.groups[gi];
+        const int32_t *list = gr.lists + size_t(it % 2) * gr.cells;
+        HIP_TRY(afe::launch_mark_listed(E.d_tab, list, upper[gi], 2, s));
+        HIP_TRY(afe::launch_mark_late2(E.d_tab, list, upper[gi], s));
+    }
+    HIP_TRY(hipEventRecord(E.ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(E.side, E.ev_fork, 0));
+    for (auto &gr : E.groups)
+        for (int sl : gr.slots) {
+            afe_cell_data *cd = E.cds[sl];
+            HIP_TRY(afe::launch_pred_post(cd->g, E.tab[sl].w, 1, E.side));
+            HIP_TRY(afe::launch_correct(cd->g, E.tab[sl].w, E.u[sl], 0, E.side));
+        }
+    HIP_TRY(hipEventRecord(E.ev_early, E.side));
+    E.forked2 = true;
     return AFE_OK;
 }
 
@@ -407,6 +444,7 @@ afe_status iterate(Engine &E, hipStream_t s) {
     for (size_t gi = 0; gi < E.groups.size(); ++gi) total += upper[gi] = int(E.groups[gi].cells);
     const int64_t all_cells = total;
     E.forked = false;
+    E.forked2 = false;
     int it = 0;
     while (total > 0 && it < max_it) {
         int R = E.shape.rounds;
@@ -429,6 +467,8 @@ afe_status iterate(Engine &E, hipStream_t s) {
         total = 0;
         for (size_t gi = 0; gi < E.groups.size(); ++gi) total += upper[gi] = E.h_counts[gi];
         if (!E.forked && total > 0 && total * kEarlyFraction <= all_cells) AFE_TRY(launch_early_post(E, it, upper, s));
+        if (E.allow_correct && E.forked && !E.forked2 && total > 0 && total * kLateCorrectFraction <= all_cells)
+            AFE_TRY(launch_early_correct(E, it, upper, s));
         if (E.prof_on && !graph) {
             for (int r = 0; r < std::min(R, afe::kMaxRounds); ++r) {
                 float ms = 0.0f;
@@ -448,8 +488,8 @@ afe_status launch_post(Engine &E, hipStream_t s) {
         for (int sl : gr.slots) {
             afe_cell_data *cd = E.cds[sl];
             const afe::DevWork &w = E.tab[sl].w;
-            HIP_TRY(afe::launch_pred_post(cd->g, w, 1, s));
-            HIP_TRY(afe::launch_correct(cd->g, w, E.u[sl], s));
+            HIP_TRY(afe::launch_pred_post(cd->g, w, 2, s));
+            HIP_TRY(afe::launch_correct(cd->g, w, E.u[sl], 1, s));
             HIP_TRY(afe::launch_step_stats(cd->g, w, s));
         }
     return AFE_OK;
@@ -508,7 +548,10 @@ afe_status batch_step_on(Engine &E, afe_batch_report *reps, int32_t n_reps, hipS
     } else {
         AFE_TRY(launch_pre(E, true, s));
     }
-    AFE_TRY(iterate(E, s));
+    E.allow_correct = true;
+    const afe_status it_st = iterate(E, s);
+    E.allow_correct = false;
+    AFE_TRY(it_st);
     AFE_TRY(join_early(E, s));
     if (graph) {
         if (!E.g_post) AFE_TRY(capture(E, &E.g_post, s, post_body, 0));
@@ -717,6 +760,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(w.gamma, size_t(h.n_cells) * 63)) != hipSuccess ||
         (e = cd->alloc(w.kuse, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.late, size_t(h.n_cells))) != hipSuccess ||
+        (e = cd->alloc(w.late2, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.dt, 1)) != hipSuccess || (e = cd->alloc(w.dt_prev, 1)) != hipSuccess ||
         (e = cd->alloc(w.guess_ok, 1)) != hipSuccess || (e = hipMemsetAsync(w.guess_ok, 0, sizeof(int32_t), s)) != hipSuccess ||
         (e = cd->alloc(w.status, kStatusWords)) != hipSuccess || (e = cd->alloc(cd->d_scalar, 1)) != hipSuccess ||
@@ -863,7 +907,12 @@ afe_status ader_cfl_dt(afe_cell_data *cd, const double *u, double cfl, double *d
     return AFE_OK;
 }
 
-afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *stream) {
+}  // extern "C"
+
+namespace {
+// Predictor of one object; with `full`, the caller goes on to correct u in
+// the same step, so the corrector may start early for cells that allow it.
+afe_status predict_impl(afe_cell_data *cd, const double *u, double dt, void *stream, bool full) {
     if (!cd || !u || !(dt > 0.0)) return fail(AFE_E_ARG, "invalid argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     Engine &E = cd->solo;
@@ -876,23 +925,33 @@ afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *str
     apply_shape(E);
     HIP_TRY(afe::launch_set_dt(cd->w, dt, s));
     AFE_TRY(launch_pre(E, false, s));
-    AFE_TRY(iterate(E, s));
+    E.allow_correct = full;
+    const afe_status it_st = iterate(E, s);
+    E.allow_correct = false;
+    AFE_TRY(it_st);
     AFE_TRY(join_early(E, s));
-    HIP_TRY(afe::launch_pred_post(cd->g, E.tab[0].w, 1, s));
+    HIP_TRY(afe::launch_pred_post(cd->g, E.tab[0].w, 2, s));
     return AFE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *stream) {
+    return predict_impl(cd, u, dt, stream, false);
 }
 
 afe_status ader_correct(afe_cell_data *cd, double *u, double dt, void *stream) {
     if (!cd || !u || !(dt > 0.0)) return fail(AFE_E_ARG, "invalid argument");
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(afe::launch_set_dt(cd->w, dt, s));
-    HIP_TRY(afe::launch_correct(cd->g, cd->w, u, s));
+    HIP_TRY(afe::launch_correct(cd->g, cd->w, u, 1, s));
     HIP_TRY(afe::launch_step_stats(cd->g, cd->w, s));
     return AFE_OK;
 }
 
 afe_status ader_step(afe_cell_data *cd, double *u, double dt, afe_step_report *rep, void *stream) {
-    AFE_TRY(ader_predict(cd, u, dt, stream));
+    AFE_TRY(predict_impl(cd, u, dt, stream, true));
     AFE_TRY(ader_correct(cd, u, dt, stream));
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(cd->h_status, cd->w.status, kStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));

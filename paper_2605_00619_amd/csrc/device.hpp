@@ -82,7 +82,8 @@ struct DevWork {
     int32_t *status; // [8]: flags, first bad cell, -, troubled count, iterations min, max, sum (64 bit)
     double *gamma;   // [n_cells][63] Anderson coefficients
     int32_t *kuse;   // [n_cells] history columns used by the update
-    int32_t *late;   // [n_cells] 1: time integrals left to the final pass (still iterating at the early pass)
+    int32_t *late;   // [n_cells] pass of the cell's time integrals: 0 early, 1 middle, 2 final
+    int32_t *late2;  // [n_cells] pass of the cell's corrector: 0 early, 1 final
     double *dt;      // [1] time step of the current step
     double *dt_prev; // [1] time step of the last successful step
     int32_t *guess_ok; // [1] 1: x holds the converged predictor of that step
@@ -148,15 +149,24 @@ struct RoundArgs {
     unsigned long long *bytes;
 };
 hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s);
-// Early time-integral pass: late[] cleared for one slot, then set for the
-// cells of the listed (slot, cell) entries (count: the list length, known on
-// the host).
+// Early passes over cells whose predictor is final while others still
+// iterate (the lists' lengths, count, are known on the host):
+//   clear_late:   late[] = 0 for one slot;
+//   relabel_late: late[] 2 -> 1 for one slot (final pass -> middle pass);
+//   mark_listed:  late[] = value for the cells of the listed entries;
+//   clear_late2:  late2[] = 0 for one slot;
+//   mark_late2:   late2[] = 1 for the listed cells and their face neighbours.
 hipError_t launch_clear_late(const DevGrid &g, const DevWork &w, hipStream_t s);
-hipError_t launch_mark_listed(const DevSlot *tab, const int32_t *list, int count, hipStream_t s);
+hipError_t launch_relabel_late(const DevGrid &g, const DevWork &w, hipStream_t s);
+hipError_t launch_mark_listed(const DevSlot *tab, const int32_t *list, int count, int value, hipStream_t s);
+hipError_t launch_clear_late2(const DevGrid &g, const DevWork &w, hipStream_t s);
+hipError_t launch_mark_late2(const DevSlot *tab, const int32_t *list, int count, hipStream_t s);
 // Time integrals of the converged predictor for the sub-tets of cells with
 // late[c] == which.
 hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, int which, hipStream_t s);
-hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, hipStream_t s);
+// Corrector (faces, right-hand side, M^-1 update of u, positivity) for the
+// cells with late2[c] == which.
+hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, int which, hipStream_t s);
 // Predictor iteration counts of the step into status[4..7].
 hipError_t launch_step_stats(const DevGrid &g, const DevWork &w, hipStream_t s);
 // Occupancy-derived persistent grid sizes for degree N, precision and

@@ -455,7 +455,8 @@ __global__ void k_pred_init(DevGrid g, DevWork w, int slot, int32_t *list, int64
     if (l < g.n_cells) {
         list[base + l] = (slot << kSlotShift) | int32_t(l);
         w.iters[l] = 0;
-        w.late[l] = 1;
+        w.late[l] = 2;
+        w.late2[l] = 1;
         w.hist[2 * l] = 0;
         w.hist[2 * l + 1] = 0;
     }
@@ -466,12 +467,38 @@ __global__ void k_clear_late(DevGrid g, DevWork w) {
     if (c < g.n_cells) w.late[c] = 0;
 }
 
-__global__ void k_mark_listed(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list, int count) {
+__global__ void k_relabel_late(DevGrid g, DevWork w) {
+    const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (c < g.n_cells && w.late[c] == 2) w.late[c] = 1;
+}
+
+__global__ void k_mark_listed(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list, int count,
+                              int value) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
     int slot, c;
     decode(list[i], slot, c);
-    tab[slot].w.late[c] = 1;
+    tab[slot].w.late[c] = value;
+}
+
+__global__ void k_clear_late2(DevGrid g, DevWork w) {
+    const int64_t c = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (c < g.n_cells) w.late2[c] = 0;
+}
+
+// One block per listed entry: the cell and, across each of its sub-tets'
+// boundary triangles, the neighbouring cell (stores of the same value).
+__global__ void __launch_bounds__(256) k_mark_late2(const DevSlot *__restrict__ tab,
+                                                    const int32_t *__restrict__ list, int count) {
+    for (int i = blockIdx.x; i < count; i += gridDim.x) {
+        int slot, c;
+        decode(list[i], slot, c);
+        const DevGrid &g = tab[slot].g;
+        const DevWork &w = tab[slot].w;
+        if (threadIdx.x == 0) w.late2[c] = 1;
+        for (int64_t k = g.sub_ptr[c] + threadIdx.x; k < g.sub_ptr[c + 1]; k += blockDim.x)
+            w.late2[g.sub_cell[g.nbr_sub[k]]] = 1;
+    }
 }
 
 __global__ void k_set_int(int32_t *p, int v) {
@@ -884,9 +911,10 @@ __global__ void __launch_bounds__(256) k_round_minv(const DevSlot *__restrict__ 
 // Corrector: u += M_i^{-1} rhs for every cell of one simulation.
 template <int NC>
 __global__ void __launch_bounds__(256) k_minv_update(DevGrid g, const double *__restrict__ X, double *__restrict__ Y,
-                                                     int tpc) {
+                                                     int tpc, const int32_t *__restrict__ late2, int which) {
     __shared__ double part[NC][kWave];
     const int lb = xcd_block();
+    if (late2[lb / tpc] != which) return;
     minv_tile<NC, 1>(g, lb / tpc, lb % tpc, X, Y, nullptr, part);
 }
 
@@ -1357,7 +1385,7 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
 // 2 A_k sum_j Z^[j'][j] G_j.  One value of the dissipation coefficient per
 // sub-triangle: the maximum over its nodes and both sides.
 template <int N>
-__global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w) {
+__global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w, int which) {
     constexpr int nf = Dim<N>::nf;
     const double dt = *w.dt;
     constexpr int tpb = 256 / nf;
@@ -1365,7 +1393,7 @@ __global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w) {
     __shared__ double G_s[tpb][nf][5];
     const int t = threadIdx.x / nf, j = threadIdx.x % nf;
     const int64_t k = int64_t(blockIdx.x) * tpb + t;
-    const bool valid = t < tpb && k < g.nsub;
+    const bool valid = t < tpb && k < g.nsub && w.late2[g.sub_cell[k]] == which;
     double Gv[5] = {0, 0, 0, 0, 0};
     double nrm[3] = {0, 0, 0}, a2 = 0.0;
     double eps = 0.0;
@@ -1429,10 +1457,11 @@ __global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w) {
 
 // rhs[l][v] = volume term - face term, gathered over the incidence lists.
 template <int N>
-__global__ void __launch_bounds__(256) k_rhs(DevGrid g, DevWork w) {
+__global__ void __launch_bounds__(256) k_rhs(DevGrid g, DevWork w, int which) {
     const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (t >= g.ndof * 5) return;
     const int64_t l = t / 5;
+    if (w.late2[g.dof_cell[l]] != which) return;
     const int v = int(t % 5);
     const double acc = ordered_gather_sum(w.vk, g.inc_idx, g.inc_ptr[l], g.inc_ptr[l + 1], 5, v);
     const double fac = ordered_gather_sum(w.fc, g.finc_idx, g.finc_ptr[l], g.finc_ptr[l + 1], 5, v);
@@ -1494,9 +1523,9 @@ __global__ void __launch_bounds__(1024) k_step_stats(DevWork w, int n_cells) {
     }
 }
 
-__global__ void k_positivity(DevGrid g, DevWork w, const double *__restrict__ u) {
+__global__ void k_positivity(DevGrid g, DevWork w, const double *__restrict__ u, int which) {
     const int64_t l = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
-    if (l >= g.ndof) return;
+    if (l >= g.ndof || w.late2[g.dof_cell[l]] != which) return;
     double q[5];
     bool finite = true;
     for (int v = 0; v < 5; ++v) {
@@ -1626,9 +1655,25 @@ hipError_t launch_clear_late(const DevGrid &g, const DevWork &w, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_mark_listed(const DevSlot *tab, const int32_t *list, int count, hipStream_t s) {
+hipError_t launch_relabel_late(const DevGrid &g, const DevWork &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_relabel_late, dim3(blocks_for(g.n_cells, 256)), dim3(256), 0, s, g, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_listed(const DevSlot *tab, const int32_t *list, int count, int value, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_mark_listed, dim3(blocks_for(count, 256)), dim3(256), 0, s, tab, list, count);
+    hipLaunchKernelGGL(k_mark_listed, dim3(blocks_for(count, 256)), dim3(256), 0, s, tab, list, count, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_clear_late2(const DevGrid &g, const DevWork &w, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_late2, dim3(blocks_for(g.n_cells, 256)), dim3(256), 0, s, g, w);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_late2(const DevSlot *tab, const int32_t *list, int count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mark_late2, dim3(unsigned(std::min(count, 4096))), dim3(256), 0, s, tab, list, count);
     return hipGetLastError();
 }
 
@@ -1646,15 +1691,16 @@ hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, int which, hipSt
     });
 }
 
-hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, hipStream_t s) {
+hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, int which, hipStream_t s) {
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        hipLaunchKernelGGL(k_face<NN>, dim3(blocks_for(g.nsub, 256 / D::nf)), dim3(256), 0, s, g, w);
-        hipLaunchKernelGGL(k_rhs<NN>, dim3(blocks_for(g.ndof * 5, 256)), dim3(256), 0, s, g, w);
+        hipLaunchKernelGGL(k_face<NN>, dim3(blocks_for(g.nsub, 256 / D::nf)), dim3(256), 0, s, g, w, which);
+        hipLaunchKernelGGL(k_rhs<NN>, dim3(blocks_for(g.ndof * 5, 256)), dim3(256), 0, s, g, w, which);
         const int tpc = (g.max_cell_dofs + 63) / 64;
-        hipLaunchKernelGGL(k_minv_update<5>, dim3(unsigned(g.n_cells) * tpc), dim3(256), 0, s, g, w.rhs, u, tpc);
-        hipLaunchKernelGGL(k_positivity, dim3(blocks_for(g.ndof, 256)), dim3(256), 0, s, g, w, u);
+        hipLaunchKernelGGL(k_minv_update<5>, dim3(unsigned(g.n_cells) * tpc), dim3(256), 0, s, g, w.rhs, u, tpc,
+                           w.late2, which);
+        hipLaunchKernelGGL(k_positivity, dim3(blocks_for(g.ndof, 256)), dim3(256), 0, s, g, w, u, which);
         return hipGetLastError();
     });
 }
