@@ -823,6 +823,11 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
 
 constexpr int kMinvUnroll = 8;
 
+// Splits of the predictor's M^-1 product for cell c in its current iteration.
+__device__ inline int minv_splits(const DevGrid &g, const DevWork &w, int c) {
+    return (!g.mixed && w.iters[c] >= kMinvSplitAfter) ? kMinvSplitK : 1;
+}
+
 // Y = M_i^{-1} X for rows [64 tile, 64 tile + 64) of cell c; X and Y DOF-major
 // with NC columns.  The 4 waves of the block split the inner index j into 4
 // contiguous ranges; their partial sums are added in a fixed wave order
@@ -830,8 +835,10 @@ constexpr int kMinvUnroll = 8;
 // matrix supplies column j: one j is a coalesced 512-byte load across the
 // wave, and X[j][:] is wave-uniform.
 // MODE 0: Y = S (predictor);  MODE 1: add Y into the SoA state u (corrector).
+// Inner index range [jb, je) (the whole row, 0..n, except in a split of the
+// predictor's tail iterations); the 4 waves take contiguous quarters of it.
 template <int NC, int MODE>
-__device__ inline void minv_tile(const DevGrid &g, int c, int tile, const double *__restrict__ X,
+__device__ inline void minv_tile(const DevGrid &g, int c, int tile, int jb, int je, const double *__restrict__ X,
                                  double *__restrict__ Y, unsigned long long *bytes, double (*part)[kWave]) {
     const int lane = threadIdx.x % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -841,16 +848,17 @@ __device__ inline void minv_tile(const DevGrid &g, int c, int tile, const double
     const int r0 = tile * kWave;
     if (r0 >= n) return;
     if (bytes != nullptr && threadIdx.x == 0) {
-        const unsigned long long rows = unsigned(min(kWave, n - r0));
-        atomicAdd(bytes, 8ull * (rows * unsigned(n) + rows * NC + (tile == 0 ? unsigned(n) * NC : 0u)));
+        // matrix and right-hand side once over the splits, the result once per row
+        const unsigned long long rows = unsigned(min(kWave, n - r0)), w = unsigned(je - jb);
+        atomicAdd(bytes, 8ull * (rows * w + (jb == 0 ? rows * NC : 0u) + (tile == 0 ? w * NC : 0u)));
     }
     const int row = r0 + lane;
     const bool ok = row < n;
     const int rowc = ok ? row : n - 1;  // clamped: out-of-range lanes read a valid address
     const gptr<double> A = (gptr<double>)(uni_ptr(g.minv + g.minv_ptr[c]) + rowc);
     const cptr<double> B = (cptr<double>)uni_ptr(X + d0 * NC);
-    const int span = (n + 3) / 4;
-    const int j0 = min(n, wv * span), j1 = min(n, j0 + span);
+    const int span = uni((je - jb + 3) / 4);
+    const int j0 = uni(min(je, jb + wv * span)), j1 = uni(min(je, j0 + span));
     double acc[NC];
 #pragma unroll
     for (int col = 0; col < NC; ++col) acc[col] = 0.0;
@@ -892,18 +900,32 @@ __device__ inline void minv_tile(const DevGrid &g, int c, int tile, const double
     }
 }
 
-// Predictor: S = M_i^{-1} R for the listed cells, work item = (entry, tile).
+// Predictor: S = M_i^{-1} R for the listed cells, work item = (entry, tile,
+// split).  From iteration kMinvSplitAfter on (few cells are left, and a tile's
+// time is one wave's chain of dependent loads) the inner index of an FP64
+// cell is split kMinvSplitK ways over workgroups, each writing its partial
+// product to Sp[split]; the Anderson kernel adds them in split order.  The
+// split depends only on the cell's iteration count, so a cell's bits do not
+// depend on what it is batched with.  spl = the item split factor of this
+// launch, kMinvSplitK whenever some listed cell may split.
 template <int NC>
 __global__ void __launch_bounds__(256) k_round_minv(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
-                                                    const int32_t *__restrict__ count, int tpc,
+                                                    const int32_t *__restrict__ count, int tpc, int spl,
                                                     unsigned long long *bytes) {
     __shared__ double part[NC][kWave];
-    const int n_items = *count * tpc;
+    const int per_entry = tpc * spl;
+    const int n_items = *count * per_entry;
     for (int item = xcd_block(); item < n_items; item += gridDim.x) {
         int slot, c;
-        decode(uni(list[item / tpc]), slot, c);
+        decode(uni(list[item / per_entry]), slot, c);
         const DevSlot &sl = tab[slot];
-        minv_tile<NC, 0>(sl.g, c, item % tpc, sl.w.R, sl.w.S, bytes, part);
+        const int rem = item % per_entry, tile = rem / spl, split = rem % spl;
+        const int sk = uni(minv_splits(sl.g, sl.w, c));
+        if (split >= sk) continue;
+        const int n = uni(int(sl.g.dof_ptr[c + 1] - sl.g.dof_ptr[c]));
+        const int per = (n + sk - 1) / sk, jb = min(n, split * per), je = min(n, jb + per);
+        double *Y = sk == 1 ? sl.w.S : sl.w.Sp + int64_t(split) * sl.g.ndof * NC;
+        minv_tile<NC, 0>(sl.g, c, tile, jb, je, sl.w.R, uni_ptr(Y), bytes, part);
         __syncthreads();
     }
 }
@@ -915,7 +937,8 @@ __global__ void __launch_bounds__(256) k_minv_update(DevGrid g, const double *__
     __shared__ double part[NC][kWave];
     const int lb = xcd_block();
     if (late2[lb / tpc] != which) return;
-    minv_tile<NC, 1>(g, lb / tpc, lb % tpc, X, Y, nullptr, part);
+    const int c = lb / tpc;
+    minv_tile<NC, 1>(g, c, lb % tpc, 0, int(g.dof_ptr[c + 1] - g.dof_ptr[c]), X, Y, nullptr, part);
 }
 
 // Mixed precision: S = D (A32 (D R)) with the FP32 scaled inverse A32 and the
@@ -1039,6 +1062,7 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int depth = w.depth;
     const bool hist_on = depth > 0 && w.iters[c] > 0;
+    const int sk = minv_splits(g, w, c);
     int k = 0, head = 0;
     bool dropped = false;
     if (hist_on) ring_state(w, c, k, head, dropped);
@@ -1061,10 +1085,30 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
             const int l = int(e / nc);
             const int col = int(e % nc);
             const int b = col / 5, v = col % 5;
-            const double *sr = w.S + base + int64_t(l) * nc + v;
+            double sv[nt];
+            if (sk == 1) {
+                const double *sr = w.S + base + int64_t(l) * nc + v;
+#pragma unroll
+                for (int a = 0; a < nt; ++a) sv[a] = sr[a * 5];
+            } else {  // split M^-1 product: its partials added in split order (all loads first)
+                const double *pr = w.Sp + base + int64_t(l) * nc + v;
+                const int64_t ps = g.ndof * nc;
+                double pv[kMinvSplitK][nt];
+#pragma unroll
+                for (int q = 0; q < kMinvSplitK; ++q)
+#pragma unroll
+                    for (int a = 0; a < nt; ++a) pv[q][a] = pr[q * ps + a * 5];
+#pragma unroll
+                for (int a = 0; a < nt; ++a) {
+                    double t = pv[0][a];
+#pragma unroll
+                    for (int q = 1; q < kMinvSplitK; ++q) t += pv[q][a];
+                    sv[a] = t;
+                }
+            }
             double acc = 0.0;
 #pragma unroll
-            for (int a = 0; a < nt; ++a) acc += g.ref->Ktau_inv[b * nt + a] * sr[a * 5];
+            for (int a = 0; a < nt; ++a) acc += g.ref->Ktau_inv[b * nt + a] * sv[a];
             const double xv = w.x[base + e];
             // FP64: G = u^n - ..., mixed: G = x - ... with S from the residual
             const double gv = (g.mixed ? xv : w.u[v * g.ndof + d0 + l]) - acc;
@@ -1638,8 +1682,8 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
             hipLaunchKernelGGL(k_round_minv32<D::nc>, grid(a.shape.g_minv, tpc), dim3(256), 0, s, a.tab, a.list,
                                a.count, tpc, a.bytes);
         else
-            hipLaunchKernelGGL(k_round_minv<D::nc>, grid(a.shape.g_minv, tpc), dim3(256), 0, s, a.tab, a.list, a.count,
-                               tpc, a.bytes);
+            hipLaunchKernelGGL(k_round_minv<D::nc>, grid(a.shape.g_minv, tpc * a.split), dim3(256), 0, s, a.tab,
+                               a.list, a.count, tpc, a.split, a.bytes);
         if (a.ev1) (void)hipEventRecord(a.ev1, s);
         hipLaunchKernelGGL(k_round_dots<NN>, grid(a.shape.g_dots, tpc), dim3(256), 0, s, a.tab, a.list, a.count, tpc);
         hipLaunchKernelGGL(k_round_solve, grid(a.shape.g_solve, 1), dim3(kWave), 0, s, a.tab, a.list, a.count, a.next,
