@@ -695,7 +695,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // Sum of p[idx[q] * stride + col] over q in [q0, q1), added in ascending q
 // (the order fixes the rounding); index and value loads are issued kGatherBatch
 // at a time, so a long incidence list costs few dependent round trips.
-constexpr int kGatherBatch = 8;
+constexpr int kGatherBatch = 16;
 __device__ inline double ordered_gather_sum(const double *__restrict__ p, const int32_t *__restrict__ idx, int q0,
                                             int q1, int stride, int col) {
     double acc = 0.0;
@@ -1187,7 +1187,7 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
 // and w.hist[2c + 1] the head slot of the history.  The scaled Cholesky
 // factor is worked on in LDS (Ls, logical rows): loaded with independent
 // loads, updated there, and its changed rows written back.
-constexpr int kSolveBatch = 8;
+constexpr int kSolveBatch = 16;
 
 __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c, int32_t entry, int32_t *next,
                                       int32_t *next_count, double (*Ls)[kMaxDepth]) {
