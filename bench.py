@@ -314,6 +314,65 @@ def run_workload(args, key: str, precision: str, log, start=None, keep_initial: 
     return res
 
 
+def large_mesh_leg(log, steps: int = 3, history_cells: int = 2048) -> dict:
+    """The spherical explosion (rho, p = 1, 1 inside r = 0.4, 0.125, 0.1 outside,
+    erf width 0.01) with artificial viscosity on the 32^3-seed mesh (32768
+    cells, +-0.25h, seed 1), N = 3, in FP64 and in mixed precision from the same
+    state, with the Anderson history pooled so that the object fits in HBM.  A
+    few whole steps each: time per step, iterations, statuses, and the distance
+    of the two final states."""
+    import numpy as np
+    import torch
+
+    from afe_inputs.fields import smoothed_sphere
+    from afe_inputs.mesh import jittered_lattice_seeds, periodic_voronoi
+    from paper_2605_00619_amd import afe
+
+    t0 = time.time()
+    mesh = periodic_voronoi(jittered_lattice_seeds(32, 0.25, 1))
+    log(f"[explosion32_p3] mesh: {mesh['n_cells']} cells in {time.time() - t0:.1f}s")
+    out, ends = {}, {}
+    for prec in ("fp64", "mixed"):
+        t0 = time.time()
+        cd = afe.CellData(mesh, 3, afe.Params(av=True, max_iter=400, history_cells=history_cells,
+                                               precision=afe.AFE_MIXED if prec == "mixed" else afe.AFE_FP64))
+        torch.cuda.synchronize()
+        setup = time.time() - t0
+        x = cd.dof_coords().cpu().numpy()
+        u = cd.prim_to_cons(torch.tensor(smoothed_sphere(np.mod(x.T, 1.0), 0.4, 0.01).T.copy(), device="cuda"))
+        b = afe.Batch()
+        b.attach(cd, u, 0.004)
+        ms, reps = [], []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = b.step(check=False)[0]
+            torch.cuda.synchronize()
+            ms.append(1e3 * (time.perf_counter() - t0))
+            reps.append(r)
+            log(f"[explosion32_p3 {prec}] {r.status} {ms[-1]:.1f} ms iters {r.iters_min}/{r.iters_mean:.2f}/"
+                f"{r.iters_max} troubled {r.n_troubled}")
+            if r.status != "AFE_OK":
+                break
+        out[prec] = {"ms_per_step": ms, "iters_mean": [r.iters_mean for r in reps],
+                     "iters_max": [r.iters_max for r in reps], "status": [r.status for r in reps],
+                     "n_troubled": [r.n_troubled for r in reps], "setup_s": setup,
+                     "device_gib": cd.device_bytes / 2**30,
+                     "dof_updates_per_s": cd.ndof * 5 / (np.mean(ms) * 1e-3)}
+        out["ndof"] = cd.ndof
+        ends[prec] = u.clone()
+        b.close()
+        cd.close()
+        del u
+        torch.cuda.empty_cache()
+    if all(all(st == "AFE_OK" for st in out[p]["status"]) for p in ("fp64", "mixed")):
+        out["mixed_rel_linf_vs_fp64"] = float((ends["mixed"] - ends["fp64"]).abs().max() / ends["fp64"].abs().max())
+    out["workload"] = ("spherical explosion with artificial viscosity, periodic Voronoi 32^3 seeds (+-0.25h, seed 1), "
+                       f"N=3, CFL 0.004, {steps} steps per precision, Anderson history pooled "
+                       f"(history_cells={history_cells})")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,6 +390,7 @@ def main() -> int:
     ap.add_argument("--no-tune", action="store_true", help="default launch shape instead of the autotuner's")
     ap.add_argument("--no-guess", action="store_true",
                     help="start every predictor iteration from u^n (default: from the previous step's predictor)")
+    ap.add_argument("--no-large", action="store_true", help="skip the 32^3-seed explosion leg")
     ap.add_argument("--no-legs", dest="legs", action="store_false",
                     help="skip the mixed-precision and mesh-variant legs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -409,6 +469,8 @@ def main() -> int:
             out["start_from_un"]["rel_linf_vs_main_final_state"] = float(
                 (p["u_end"] - main_run["u_end"]).abs().max() / main_run["u_end"].abs().max())
             del p
+    if args.legs and args.precision == "fp64" and not args.no_large:
+        out["large_mesh"] = large_mesh_leg(log)
     u0_np = main_run["u_initial"].cpu().numpy() if main_run.get("u_initial") is not None else None
     mesh, dt = main_run["mesh"], main_run["dt"]
     del main_run, r

@@ -86,6 +86,13 @@ typedef struct {
                          /* step succeeded on the same state and the cell is not      */
                          /* troubled.  The fixed point, hence the result up to the    */
                          /* stop test, is the same; fewer iterations are needed.      */
+    int32_t history_cells; /* 0: every cell stores its whole Anderson history          */
+                         /* (accel_depth difference pairs of its space-time block);   */
+                         /* > 0: every cell stores 8 pairs in place and at most this   */
+                         /* many cells at once take the other accel_depth - 8 from a   */
+                         /* shared pool (memory for large meshes).  The results are   */
+                         /* the same bits; a step in which more cells need the pool   */
+                         /* fails with AFE_E_HBM_BUDGET.                               */
 } afe_params;
 
 typedef struct {

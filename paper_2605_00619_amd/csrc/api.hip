@@ -181,8 +181,12 @@ struct afe_batch {
 namespace {
 
 // Device bytes of one simulation (the allocations of build_afe_cell_data).
+// In-place history slots per cell and pool slots for accel_depth `depth` and
+// afe_params.history_cells.
+int hist_small_of(int depth, int history_cells) { return history_cells > 0 ? std::min(depth, 8) : depth; }
+
 size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub, int max_cell_dofs, int depth,
-                      bool mixed) {
+                      bool mixed, int history_cells) {
     const size_t nc = size_t(5) * (N + 1);
     const size_t np = size_t(N + 1) * (N + 2) * (N + 3) / 6, nf = size_t(N + 1) * (N + 2) / 2;
     const size_t n_cells = cell_dofs.size();
@@ -192,7 +196,10 @@ size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub
         if (mixed) b += size_t(n) * size_t((n + 31) & ~int64_t(31)) * sizeof(float);
         ndof += size_t(n);
     }
-    b += ndof * nc * sizeof(double) * (5 + 2 * size_t(std::max(depth, 1)));
+    const int hs = hist_small_of(depth, history_cells);
+    b += ndof * nc * sizeof(double) * (5 + 2 * size_t(std::max(hs, 1)));
+    if (hs < depth)
+        b += 2 * size_t(history_cells) * size_t(depth - hs) * size_t(max_cell_dofs) * nc * sizeof(double);
     if (mixed) b += ndof * nc * sizeof(float);
     else b += size_t(afe::kMinvSplitK) * ndof * nc * sizeof(double);  // split M^-1 partials
     b += n_cells * size_t((max_cell_dofs + 63) / 64) * 130 * sizeof(double);
@@ -208,6 +215,7 @@ size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub
 afe_status check_params(const afe_params *p) {
     if (p->precision != AFE_FP64 && p->precision != AFE_MIXED) return fail(AFE_E_ARG, "unknown precision");
     if (p->predictor_guess != 0 && p->predictor_guess != 1) return fail(AFE_E_ARG, "predictor_guess must be 0 or 1");
+    if (p->history_cells < 0) return fail(AFE_E_ARG, "history_cells must be >= 0");
     if (p->accel_depth < 0 || p->accel_depth > 63) return fail(AFE_E_ARG, "accel_depth must be in [0, 63]");
     if (p->max_iter < 1) return fail(AFE_E_ARG, "max_iter must be >= 1");
     if (!(p->gamma > 1.0) || p->mu < 0.0 || !(p->tol >= 0.0))
@@ -526,6 +534,7 @@ afe_status profile_read(Engine &E, double *kernel_ms, int64_t *launches, double 
 }
 
 afe_status status_of(int flags) {
+    if (flags & afe::kStatusHistoryPool) return AFE_E_HBM_BUDGET;  // the root cause of anything after it
     if (flags & afe::kStatusNonfinite) return AFE_E_NONFINITE;
     if (flags & afe::kStatusNoConv) return AFE_E_NO_CONVERGENCE;
     if (flags & afe::kStatusPositivity) return AFE_E_POSITIVITY;
@@ -537,6 +546,7 @@ const char *status_text(afe_status st) {
         case AFE_E_NONFINITE: return "non-finite state after the update";
         case AFE_E_NO_CONVERGENCE: return "predictor did not converge";
         case AFE_E_POSITIVITY: return "density or pressure not positive";
+        case AFE_E_HBM_BUDGET: return "more cells needed the Anderson history pool than history_cells";
         default: return "";
     }
 }
@@ -640,7 +650,8 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     }
     std::vector<int64_t> cell_dofs(h.n_cells);
     for (int c = 0; c < h.n_cells; ++c) cell_dofs[c] = h.dof_ptr[c + 1] - h.dof_ptr[c];
-    size_t need = estimate_bytes(N, cell_dofs, h.nsub, h.max_cell_dofs, depth, params->precision == AFE_MIXED);
+    size_t need = estimate_bytes(N, cell_dofs, h.nsub, h.max_cell_dofs, depth, params->precision == AFE_MIXED,
+                                 params->history_cells);
     if (params->hbm_budget > 0 && need > params->hbm_budget) {
         delete cd;
         return fail(AFE_E_HBM_BUDGET, "needs " + std::to_string(need) + " bytes, budget " +
@@ -735,7 +746,11 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     g.ref = dref;
     const size_t nc = size_t(g.nc);
     const size_t nd = size_t(h.ndof);
-    const int dslots = std::max(depth, 1);
+    g.hist_small = hist_small_of(depth, params->history_cells);
+    g.pool_cap = g.hist_small < depth ? params->history_cells : 0;
+    g.pool_stride = int64_t(depth - g.hist_small) * h.max_cell_dofs * int64_t(g.nc);
+    const int dslots = std::max(g.hist_small, 1);
+    const size_t pool = g.pool_cap > 0 ? size_t(g.pool_cap) * size_t(g.pool_stride) : 1;
     w.depth = depth;
     w.tol = params->tol;
     w.max_iter = params->max_iter;
@@ -749,7 +764,9 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(w.gprev, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.part, size_t(h.n_cells) * ((h.max_cell_dofs + 63) / 64) * 130)) != hipSuccess ||
         (e = cd->alloc(w.dF, nd * nc * dslots)) != hipSuccess ||
-        (e = cd->alloc(w.dG, nd * nc * dslots)) != hipSuccess ||
+        (e = cd->alloc(w.dG, nd * nc * dslots)) != hipSuccess || (e = cd->alloc(w.dFp, pool)) != hipSuccess ||
+        (e = cd->alloc(w.dGp, pool)) != hipSuccess || (e = cd->alloc(w.pool_slot, size_t(h.n_cells))) != hipSuccess ||
+        (e = cd->alloc(w.pool_count, 1)) != hipSuccess ||
         (e = cd->alloc(w.gram, size_t(h.n_cells) * (2 * 63 * 63 + 63))) != hipSuccess ||
         (e = cd->alloc(w.hist, size_t(h.n_cells) * 2)) != hipSuccess ||
         (e = cd->alloc(w.rk, size_t(h.nsub) * h.np * nc)) != hipSuccess ||
@@ -821,7 +838,8 @@ afe_status afe_estimate_bytes(const afe_mesh *mesh, int32_t N, const afe_params 
         nsub += 2 * Ec;
         max_dofs = std::max<int>(max_dofs, int(dofs[c]));
     }
-    *bytes = estimate_bytes(N, dofs, nsub, max_dofs, params->accel_depth, params->precision == AFE_MIXED);
+    *bytes = estimate_bytes(N, dofs, nsub, max_dofs, params->accel_depth, params->precision == AFE_MIXED,
+                            params->history_cells);
     return AFE_OK;
 }
 

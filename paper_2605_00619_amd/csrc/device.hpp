@@ -35,6 +35,11 @@ struct DevGrid {
     int av;
     int mixed;                // 1: FP32 preconditioner for the predictor iteration
     int guess;                // 1: predictor start extrapolated from the previous step
+    // Anderson history: slots 0..hist_small-1 of a cell in place (DOF-major, as
+    // the cell's block), slots hist_small..depth-1 in the cell's pool slot
+    // (hist_small = depth: no pool)
+    int hist_small, pool_cap;
+    int64_t pool_stride;      // doubles per pool slot: (depth - hist_small) * max_cell_dofs * nc
     // connectivity and geometry
     const int64_t *dof_ptr;   // [n_cells + 1]
     const int64_t *sub_ptr;   // [n_cells + 1]
@@ -68,8 +73,11 @@ struct DevWork {
     double *fprev;   // [ndof][nc] residual G(x) - x of the current iterate
     double *gprev;   // [ndof][nc] G(x) of the current iterate
     double *part;    // [n_cells][tiles of 64 DOFs][2 * 64 + 2] partial dots and norms
-    double *dF;      // per cell: depth columns of n_c * nc (append-only)
+    double *dF;      // per cell: hist_small columns of n_c * nc
     double *dG;
+    double *dFp, *dGp;   // history pool: pool_cap slots of pool_stride doubles
+    int32_t *pool_slot;  // [n_cells] pool slot of the cell in this step, -1: none
+    int32_t *pool_count; // [1] pool slots handed out in this step
     double *gram;    // [n_cells][63][63] Cholesky rows, [n_cells][63][63] Gram, [n_cells][63] scales
     int32_t *hist;   // [n_cells][2]: stored difference pairs
     double *trace;   // [nsub][nf][20]: qbar (5), Fbar (15) at face nodes
@@ -105,7 +113,7 @@ constexpr int kSlotShift = 24;
 constexpr int kMaxSlots = 64;
 constexpr int kMaxCellsPerSlot = 1 << kSlotShift;
 
-enum : int { kStatusNoConv = 1, kStatusPositivity = 2, kStatusNonfinite = 4 };
+enum : int { kStatusNoConv = 1, kStatusPositivity = 2, kStatusNonfinite = 4, kStatusHistoryPool = 8 };
 
 // Grid sizes of one predictor iteration's kernels: workgroups of a
 // persistent grid, 0 = one workgroup per work item.

@@ -457,6 +457,7 @@ __global__ void k_pred_init(DevGrid g, DevWork w, int slot, int32_t *list, int64
         w.iters[l] = 0;
         w.late[l] = 2;
         w.late2[l] = 1;
+        w.pool_slot[l] = -1;
         w.hist[2 * l] = 0;
         w.hist[2 * l + 1] = 0;
     }
@@ -1035,6 +1036,14 @@ __global__ void __launch_bounds__(256) k_round_minv32(const DevSlot *__restrict_
 constexpr int kDrop = 8;
 constexpr int kPartStride = 2 * (kMaxDepth + 1) + 2;
 
+// Column of ring slot s of cell c in a history area (dF or dG): in place for
+// s < hist_small, else in the cell's pool slot.
+__device__ inline double *hist_col(const DevGrid &g, const DevWork &w, double *in_place, double *pool, int c,
+                                   int64_t base, int64_t len, int s) {
+    if (s < g.hist_small) return in_place + base * g.hist_small + int64_t(s) * len;
+    return pool + int64_t(w.pool_slot[c]) * g.pool_stride + int64_t(s - g.hist_small) * len;
+}
+
 // history bookkeeping: (count kept, head slot) after the drop this iteration makes
 __device__ inline void ring_state(const DevWork &w, int c, int &k, int &head, bool &dropped) {
     k = w.hist[2 * c];
@@ -1069,8 +1078,7 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
     const int snew = hist_on ? (head + k) % depth : 0;
     const int64_t len = int64_t(n) * nc;
     const int64_t base = d0 * nc;
-    double *dF = w.dF + base * depth;
-    double *dG = w.dG + base * depth;
+
     const int64_t e0 = int64_t(tile) * 64 * nc;
     const int64_t e1 = min(len, e0 + int64_t(64) * nc);
     double fe[kPer], dfe[kPer];
@@ -1117,8 +1125,8 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
             gmx = fmax(gmx, fabs(gv));
             if (hist_on) {
                 const double dfn = fv - w.fprev[base + e];
-                dF[int64_t(snew) * len + e] = dfn;
-                dG[int64_t(snew) * len + e] = gv - w.gprev[base + e];
+                hist_col(g, w, w.dF, w.dFp, c, base, len, snew)[e] = dfn;
+                hist_col(g, w, w.dG, w.dGp, c, base, len, snew)[e] = gv - w.gprev[base + e];
                 dfe[q] = dfn;
             }
             fe[q] = fv;
@@ -1146,7 +1154,7 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
 #pragma unroll
                     for (int u = 0; u < kDotCols; ++u) {
                         const int j = j0 + u;
-                        d[u] = j < k ? dF[int64_t((head + j) % depth) * len + ie[q]] : dfe[q];
+                        d[u] = j < k ? hist_col(g, w, w.dF, w.dFp, c, base, len, (head + j) % depth)[ie[q]] : dfe[q];
                     }
 #pragma unroll
                     for (int u = 0; u < kDotCols; ++u) {
@@ -1347,6 +1355,27 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
         w.kuse[c] = kuse;
         w.hist[2 * c] = kuse;
         w.hist[2 * c + 1] = head;
+        if (g.hist_small < depth) {
+            // the slot the next iteration appends to: a pool slot is taken the
+            // first time it lies beyond the in-place columns
+            int k2 = kuse, h2 = kuse == 0 ? 0 : head;  // as ring_state reads it back
+            if (k2 >= depth) {
+                const int drop = min(kDrop, k2);
+                h2 = (h2 + drop) % depth;
+                k2 -= drop;
+            }
+            if ((h2 + k2) % depth >= g.hist_small && w.pool_slot[c] < 0) {
+                const int p = atomicAdd(w.pool_count, 1);
+                if (p < g.pool_cap) {
+                    w.pool_slot[c] = p;
+                } else {  // pool exhausted: the step fails; the cell restarts its history in place
+                    atomicOr(&w.status[0], kStatusHistoryPool);
+                    atomicMin(&w.status[1], c);
+                    w.hist[2 * c] = 0;
+                    w.hist[2 * c + 1] = 0;
+                }
+            }
+        }
     }
     __syncthreads();  // Ls is reused by the next item
 }
@@ -1403,7 +1432,7 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
         const int depth = w.depth;
         const int head = w.hist[2 * c + 1];
         const cptr<double> gam = (cptr<double>)uni_ptr(w.gamma + int64_t(c) * kMaxDepth);
-        const double *dG = w.dG + base * (depth > 0 ? depth : 1);
+
         const int64_t e0 = int64_t(tile) * 64 * nc;
         const int64_t e1 = min(len, e0 + int64_t(64) * nc);
         for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
@@ -1412,11 +1441,12 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
             for (; j + kUpdBatch <= kuse; j += kUpdBatch) {
                 double d[kUpdBatch];
 #pragma unroll
-                for (int u = 0; u < kUpdBatch; ++u) d[u] = dG[int64_t((head + j + u) % depth) * len + e];
+                for (int u = 0; u < kUpdBatch; ++u)
+                    d[u] = hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j + u) % depth)[e];
 #pragma unroll
                 for (int u = 0; u < kUpdBatch; ++u) xv -= gam[j + u] * d[u];
             }
-            for (; j < kuse; ++j) xv -= gam[j] * dG[int64_t((head + j) % depth) * len + e];
+            for (; j < kuse; ++j) xv -= gam[j] * hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j) % depth)[e];
             w.x[base + e] = xv;
         }
     }
@@ -1522,6 +1552,7 @@ __global__ void k_reset_status(DevWork w, int n_cells) {
         w.status[5] = 0;
         w.status[6] = 0;
         w.status[7] = 0;
+        *w.pool_count = 0;
     }
 }
 
