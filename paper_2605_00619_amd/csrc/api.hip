@@ -201,7 +201,7 @@ size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub
     if (hs < depth)
         b += 2 * size_t(history_cells) * size_t(depth - hs) * size_t(max_cell_dofs) * nc * sizeof(double);
     if (mixed) b += ndof * nc * sizeof(float);
-    b += size_t(afe::kMinvSplitK) * ndof * nc * sizeof(double);  // split M^-1 partials
+    else b += size_t(afe::kMinvSplitK) * ndof * nc * sizeof(double);  // split M^-1 partials
     b += n_cells * size_t((max_cell_dofs + 63) / 64) * 130 * sizeof(double);
     b += size_t(nsub) * np * nc * sizeof(double);
     b += size_t(nsub) * nf * 25 * sizeof(double) + size_t(nsub) * np * 5 * sizeof(double);  // traces, faces, volume
@@ -331,7 +331,7 @@ afe_status launch_round(Engine &E, int it, const std::vector<int> &upper, int pr
         a.next_count = gr.counts + nxt;
         a.n_upper = upper.empty() ? -1 : upper[gi];
         // every listed cell is at iteration it; graph chunks replay at any it
-        a.split = (upper.empty() || it >= afe::kMinvSplitAfter) ? afe::kMinvSplitK : 1;
+        a.split = (!gr.mixed && (upper.empty() || it >= afe::kMinvSplitAfter)) ? afe::kMinvSplitK : 1;
         a.max_cell_dofs = gr.max_cell_dofs;
         a.max_cell_subtets = gr.max_cell_subtets;
         a.shape = gr.shape;
@@ -760,7 +760,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(w.R32, g.mixed ? nd * nc : 1)) != hipSuccess ||
         (e = cd->alloc(w.x, nd * nc)) != hipSuccess || (e = cd->alloc(w.R, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.S, nd * nc)) != hipSuccess || (e = cd->alloc(w.fprev, nd * nc)) != hipSuccess ||
-        (e = cd->alloc(w.Sp, size_t(afe::kMinvSplitK) * nd * nc)) != hipSuccess ||
+        (e = cd->alloc(w.Sp, g.mixed ? 1 : size_t(afe::kMinvSplitK) * nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.gprev, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.part, size_t(h.n_cells) * ((h.max_cell_dofs + 63) / 64) * 130)) != hipSuccess ||
         (e = cd->alloc(w.dF, nd * nc * dslots)) != hipSuccess ||

@@ -68,7 +68,7 @@ struct DevWork {
     double *R;       // [ndof][nc] assembled stiffness term (FP64 path)
     float *R32;      // [ndof][nc] mixed: scaled FP32 residual
     double *S;       // [ndof][nc] M^{-1} R
-    double *Sp;      // [4][ndof][nc] partial products of a split M^{-1} (tail iterations)
+    double *Sp;      // [4][ndof][nc] FP64: partial products of a split M^{-1} (tail iterations)
     double *rk;      // [nsub][np][nc] per-sub-tet contributions
     double *fprev;   // [ndof][nc] residual G(x) - x of the current iterate
     double *gprev;   // [ndof][nc] G(x) of the current iterate
@@ -147,7 +147,7 @@ hipError_t launch_set_count(int32_t *count, int value, hipStream_t s);
 // length (grids are sized from it, persistent ones capped by it; -1 when
 // unknown, which needs persistent grids); max_cell_dofs and
 // max_cell_subtets are maxima over the group.
-// The predictor's M^-1 product of a cell splits its inner index over
+// The predictor's M^-1 product of an FP64 cell splits its inner index over
 // kMinvSplitK workgroups per row tile from iteration kMinvSplitAfter on.
 constexpr int kMinvSplitK = 4;
 constexpr int kMinvSplitAfter = 3;

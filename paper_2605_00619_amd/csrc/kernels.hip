@@ -826,7 +826,7 @@ constexpr int kMinvUnroll = 8;
 
 // Splits of the predictor's M^-1 product for cell c in its current iteration.
 __device__ inline int minv_splits(const DevGrid &g, const DevWork &w, int c) {
-    return w.iters[c] >= kMinvSplitAfter ? kMinvSplitK : 1;
+    return (!g.mixed && w.iters[c] >= kMinvSplitAfter) ? kMinvSplitK : 1;
 }
 
 // Y = M_i^{-1} X for rows [64 tile, 64 tile + 64) of cell c; X and Y DOF-major
@@ -903,7 +903,7 @@ __device__ inline void minv_tile(const DevGrid &g, int c, int tile, int jb, int 
 
 // Predictor: S = M_i^{-1} R for the listed cells, work item = (entry, tile,
 // split).  From iteration kMinvSplitAfter on (few cells are left, and a tile's
-// time is one wave's chain of dependent loads) the inner index of a
+// time is one wave's chain of dependent loads) the inner index of an FP64
 // cell is split kMinvSplitK ways over workgroups, each writing its partial
 // product to Sp[split]; the Anderson kernel adds them in split order.  The
 // split depends only on the cell's iteration count, so a cell's bits do not
@@ -944,43 +944,37 @@ __global__ void __launch_bounds__(256) k_minv_update(DevGrid g, const double *__
 
 // Mixed precision: S = D (A32 (D R)) with the FP32 scaled inverse A32 and the
 // FP32 right-hand side X32 = D R (written by the assembly); FP32
-// accumulation, result scaled back to FP64.  Same tiling and tail split as
-// k_round_minv (a split's partial, scaled, goes to Sp[split]).
+// accumulation, result scaled back to FP64.  Same tiling as minv_tile.
 template <int NC>
 __global__ void __launch_bounds__(256) k_round_minv32(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
-                                                      const int32_t *__restrict__ count, int tpc, int spl,
+                                                      const int32_t *__restrict__ count, int tpc,
                                                       unsigned long long *bytes) {
     __shared__ float part[NC][kWave];
     const int lane = threadIdx.x % kWave;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const int per_entry = tpc * spl;
-    const int n_items = *count * per_entry;
+    const int n_items = *count * tpc;
     for (int item = xcd_block(); item < n_items; item += gridDim.x) {
         int slot, c;
-        decode(uni(list[item / per_entry]), slot, c);
+        decode(uni(list[item / tpc]), slot, c);
         const DevGrid &g = tab[slot].g;
         const DevWork &w = tab[slot].w;
-        const int rem = item % per_entry, tile = rem / spl, split = rem % spl;
-        const int sk = uni(minv_splits(g, w, c));
-        if (split >= sk) continue;
+        const int tile = item % tpc;
         const int64_t d0 = uni64(g.dof_ptr[c]);
         const int n = uni(int(g.dof_ptr[c + 1] - d0));
-        const int per = (n + sk - 1) / sk, jb = uni(min(n, split * per)), je = uni(min(n, jb + per));
-        double *Y = uni_ptr(sk == 1 ? w.S : w.Sp + int64_t(split) * g.ndof * NC);
         const int64_t ld = minv32_ld(n);
         const int r0 = tile * kWave;
         if (r0 >= n) continue;
         if (bytes != nullptr && threadIdx.x == 0) {
-            const unsigned long long rows = unsigned(min(kWave, n - r0)), wd = unsigned(je - jb);
-            atomicAdd(bytes, 4ull * rows * wd + (jb == 0 ? 8ull * rows * NC : 0ull) + (tile == 0 ? 4ull * wd * NC : 0ull));
+            const unsigned long long rows = unsigned(min(kWave, n - r0));
+            atomicAdd(bytes, 4ull * rows * unsigned(n) + 8ull * rows * NC + (tile == 0 ? 4ull * unsigned(n) * NC : 0ull));
         }
         const int row = r0 + lane;
         const bool ok = row < n;
         const int rowc = ok ? row : n - 1;
         const gptr<float> A = (gptr<float>)(uni_ptr(g.minv32 + g.minv32_ptr[c]) + rowc);
         const cptr<float> B = (cptr<float>)uni_ptr(w.R32 + d0 * NC);
-        const int span = uni((je - jb + 3) / 4);
-        const int j0 = uni(min(je, jb + wv * span)), j1 = uni(min(je, j0 + span));
+        const int span = (n + 3) / 4;
+        const int j0 = min(n, wv * span), j1 = min(n, j0 + span);
         float acc[NC];
 #pragma unroll
         for (int col = 0; col < NC; ++col) acc[col] = 0.0f;
@@ -1016,7 +1010,7 @@ __global__ void __launch_bounds__(256) k_round_minv32(const DevSlot *__restrict_
 #pragma unroll
             for (int col = 0; col < NC; ++col) {
                 const float v = part[col][lane] + acc[col];
-                Y[(d0 + row) * NC + col] = sc * double(v);
+                w.S[(d0 + row) * NC + col] = sc * double(v);
             }
         }
         __syncthreads();
@@ -1716,8 +1710,8 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
                            per);
         if (a.ev0) (void)hipEventRecord(a.ev0, s);
         if (a.mixed)
-            hipLaunchKernelGGL(k_round_minv32<D::nc>, grid(a.shape.g_minv, tpc * a.split), dim3(256), 0, s, a.tab,
-                               a.list, a.count, tpc, a.split, a.bytes);
+            hipLaunchKernelGGL(k_round_minv32<D::nc>, grid(a.shape.g_minv, tpc), dim3(256), 0, s, a.tab, a.list,
+                               a.count, tpc, a.bytes);
         else
             hipLaunchKernelGGL(k_round_minv<D::nc>, grid(a.shape.g_minv, tpc * a.split), dim3(256), 0, s, a.tab,
                                a.list, a.count, tpc, a.split, a.bytes);
