@@ -44,6 +44,45 @@ __device__ inline double wave_min(double v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
     return v;
 }
+// v of lane i (i the same in every lane), in every lane
+__device__ inline double lane_bcast(double v, int i) {
+    const unsigned long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(int(unsigned(b)), i);
+    const int hi = __builtin_amdgcn_readlane(int(unsigned(b >> 32)), i);
+    return __hiloint2double(hi, lo);
+}
+
+// Triangular solves of one wave, column by column, with the factor rows in
+// LDS (L[j][i] = Ls[j][i], j > i): unknown i is acc_i / L[i][i] (rinv of lane
+// i holds 1 / L[i][i]), broadcast from lane i, and lane j > i subtracts
+// L[j][i] (lower) or L[i][j] (upper, the transposed factor) times it from its
+// running residual acc_j.  Steps go in blocks of kSubBlock whose LDS reads are
+// issued together.  n is the same in every lane; the result is in lane i.
+constexpr int kSubBlock = 4;
+template <bool kUpper>
+__device__ inline double tri_solve(const double (*Ls)[kMaxDepth], double acc, double rinv, int n) {
+    const int lane = threadIdx.x % kWave, lr = min(lane, kMaxDepth - 1);
+    double x = 0.0;
+    for (int b = 0; b < n; b += kSubBlock) {
+        double l[kSubBlock];
+#pragma unroll
+        for (int u = 0; u < kSubBlock; ++u) {
+            const int i = max(min(kUpper ? n - 1 - (b + u) : b + u, kMaxDepth - 1), 0);
+            l[u] = kUpper ? Ls[i][lr] : Ls[lr][i];
+        }
+        // no branches inside the block, so that its reads stay ahead of it
+#pragma unroll
+        for (int u = 0; u < kSubBlock; ++u) {
+            const bool step = b + u < n;
+            const int i = max(min(kUpper ? n - 1 - (b + u) : b + u, kWave - 1), 0);
+            const double xi = lane_bcast(acc * rinv, i);
+            x = (step && lane == i) ? xi : x;
+            const bool upd = step && (kUpper ? lane < i : (lane > i && lane < n));
+            acc = upd ? fma(-l[u], xi, acc) : acc;
+        }
+    }
+    return x;
+}
 
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // The per-cell kernels use several blocks per cell that share the cell's
@@ -1028,7 +1067,8 @@ __global__ void __launch_bounds__(256) k_round_minv32(const DevSlot *__restrict_
 //                  tests convergence, extends (or rebuilds after dropping the
 //                  oldest pairs) the Jacobi-scaled Cholesky factor of the
 //                  Gram matrix of dF, solves for gamma, builds the next list;
-//   k_round_update (item = entry, tile): x <- G(x) - sum_j gamma_j dG_j.
+//   k_round_update (item = entry, chunk of 256 values):
+//                  x <- G(x) - sum_j gamma_j dG_j.
 // Difference pairs live in a ring of `depth` slots, logical order oldest
 // first; a column adding no new direction is not appended; when the ring is
 // full the 8 oldest pairs are dropped.  Depth 0 is the plain fixed-point map.
@@ -1194,7 +1234,11 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
 // One wave: w.gamma[c][0..kuse) receives the coefficients, w.kuse[c] = kuse
 // and w.hist[2c + 1] the head slot of the history.  The scaled Cholesky
 // factor is worked on in LDS (Ls, logical rows): loaded with independent
-// loads, updated there, and its changed rows written back.
+// loads, updated there, and its changed rows written back.  Triangular
+// solves go column by column: unknown i is broadcast from lane i and every
+// lane j updates its own running residual with L[j][i] (or L[i][j] for the
+// transposed factor), so a step is a broadcast and a fused multiply-add
+// rather than a reduction over the wave; lane i keeps 1 / L[i][i].
 constexpr int kSolveBatch = 16;
 
 __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c, int32_t entry, int32_t *next,
@@ -1249,21 +1293,22 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
     double *Lc = w.gram + int64_t(c) * kMaxDepth * kMaxDepth;             // scaled Cholesky, logical rows
     double *Hc = w.gram + cells_sq + int64_t(c) * kMaxDepth * kMaxDepth;  // Gram of dF, by slot
     double *dsc = w.gram + 2 * cells_sq + int64_t(c) * kMaxDepth;         // column scales, by slot
+    const int lr = min(lane, kMaxDepth - 1);  // this lane's row of the factor
+    double rinv = 0.0;                         // lane i: 1 / L[i][i]
+    k = uni(k);  // the same in every lane
+    head = uni(head);
     if (dropped) {
         for (int i = 0; i < k; ++i) {
+            // row i of the rebuilt factor: L[0:i, 0:i] y = scaled H[i][0:i]
             const int si = (head + i) % depth;
             const int sl = (head + lane) % depth;
             const double rhs = (lane < i) ? Hc[si * kMaxDepth + sl] * dsc[si] * dsc[sl] : 0.0;
-            double y = 0.0;
-            for (int r = 0; r < i; ++r) {
-                const double lrj = (lane < r) ? Ls[r][lane] : 0.0;
-                const double sm = wave_sum(lrj * y);
-                const double yr = (__shfl(rhs, r, kWave) - sm) / Ls[r][r];
-                if (lane == r) y = yr;
-            }
+            const double y = tri_solve<false>(Ls, rhs, rinv, i);
             const double ysq = wave_sum(lane < i ? y * y : 0.0);
+            const double lii = sqrt(fmax(1.0 + 1e-12 - ysq, 1e-10));
             if (lane < i) Ls[i][lane] = y;
-            if (lane == 0) Ls[i][i] = sqrt(fmax(1.0 + 1e-12 - ysq, 1e-10));
+            if (lane == 0) Ls[i][i] = lii;
+            if (lane == i) rinv = 1.0 / lii;
             __syncthreads();
         }
     } else {
@@ -1276,6 +1321,7 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
                 if (i0 + u < k && lane <= i0 + u) Ls[i0 + u][lane] = r[u];
         }
         __syncthreads();
+        if (lane < k) rinv = 1.0 / Ls[lr][lr];
     }
     // reduced dots: h_j = <dF_j, dF_new>, b_j = <dF_j, f>, j = 0..k (k = new column)
     double hj = 0.0, bj_raw = 0.0;
@@ -1301,47 +1347,33 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
     const double dk = hkk > 0.0 ? 1.0 / sqrt(hkk) : 0.0;
     const int sl = (head + (lane < k ? lane : 0)) % depth;
     const double dj = (lane < k) ? dsc[sl] : 0.0;
-    const double rhs = (lane < k) ? hj * dj * dk : 0.0;
-    double y = 0.0;
-    for (int i = 0; i < k; ++i) {
-        const double lij = (lane < i) ? Ls[i][lane] : 0.0;
-        const double sm = wave_sum(lij * y);
-        const double yi = (__shfl(rhs, i, kWave) - sm) / Ls[i][i];
-        if (lane == i) y = yi;
-    }
+    // new row of the factor: L y = scaled h
+    const double y = tri_solve<false>(Ls, (lane < k) ? hj * dj * dk : 0.0, rinv, k);
     const double ysq = wave_sum(lane < k ? y * y : 0.0);
     const double diag = 1.0 + 1e-12 - ysq;
     const bool add = (hkk > 0.0) && (diag > 1e-10);
-    const int kuse = add ? k + 1 : k;
+    const int kuse = uni(add ? k + 1 : k);
+    const double lkk = add ? sqrt(diag) : 1.0;
     if (add) {
         if (lane < k) {
             Hc[snew * kMaxDepth + sl] = hj;
             Hc[sl * kMaxDepth + snew] = hj;
+            Ls[k][lane] = y;
         }
         if (lane == 0) {
             Hc[snew * kMaxDepth + snew] = hkk;
             dsc[snew] = dk;
         }
+        if (lane == k) {
+            Ls[k][k] = lkk;
+            rinv = 1.0 / lkk;
+        }
     }
+    __syncthreads();
     const double scl = (lane < k) ? dj : ((lane == k) ? dk : 0.0);
-    const double bj = (lane < kuse) ? bj_raw * scl : 0.0;
-    double z = 0.0;
-    for (int i = 0; i < kuse; ++i) {
-        const double lij = (lane < i) ? ((i == k) ? y : Ls[i][lane]) : 0.0;
-        const double sm = wave_sum(lij * z);
-        const double lii = (i == k) ? sqrt(diag) : Ls[i][i];
-        const double zi = (__shfl(bj, i, kWave) - sm) / lii;
-        if (lane == i) z = zi;
-    }
-    double xs = 0.0;
-    for (int i = kuse - 1; i >= 0; --i) {
-        const double yi_new = __shfl(y, i, kWave);  // L[k][i] of the new row
-        const double lji = (lane > i && lane < kuse) ? ((lane == k) ? yi_new : Ls[lane < k ? lane : 0][i]) : 0.0;
-        const double sm = wave_sum(lji * xs);
-        const double lii = (i == k) ? sqrt(diag) : Ls[i][i];
-        const double xi = (__shfl(z, i, kWave) - sm) / lii;
-        if (lane == i) xs = xi;
-    }
+    // L z = scaled b, then L^T x = z
+    const double z = tri_solve<false>(Ls, (lane < kuse) ? bj_raw * scl : 0.0, rinv, kuse);
+    const double xs = tri_solve<true>(Ls, z, rinv, kuse);
     if (lane < kuse) gam[lane] = xs * scl;
     // write back the rows that changed: all after a rebuild, else the new one
     if (dropped)
@@ -1349,7 +1381,7 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
             if (lane <= i) Lc[i * kMaxDepth + lane] = Ls[i][lane];
     if (add) {
         if (lane < k) Lc[k * kMaxDepth + lane] = y;
-        if (lane == 0) Lc[k * kMaxDepth + k] = sqrt(diag);
+        if (lane == 0) Lc[k * kMaxDepth + k] = lkk;
     }
     if (lane == 0) {
         w.kuse[c] = kuse;
@@ -1412,43 +1444,39 @@ __global__ void __launch_bounds__(64) k_round_solve(const DevSlot *__restrict__ 
 
 constexpr int kUpdBatch = 8;
 
+// Work item = (entry, chunk of 256 space-time values of the cell), one value
+// per thread, so a cell's history columns are read by as many waves as it has
+// chunks (in the last iterations few cells are left and each has a long history).
 template <int N>
 __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
-                                                      const int32_t *__restrict__ count, int tpc) {
+                                                      const int32_t *__restrict__ count, int per) {
     constexpr int nc = Dim<N>::nc;
-    const int n_items = *count * tpc;
+    const int n_items = *count * per;
     for (int item = xcd_block(); item < n_items; item += gridDim.x) {
         int slot, c;
-        decode(list[item / tpc], slot, c);
+        decode(list[item / per], slot, c);
         const DevGrid &g = tab[slot].g;
         const DevWork &w = tab[slot].w;
-        const int tile = item % tpc;
         const int64_t d0 = g.dof_ptr[c];
-        const int n = int(g.dof_ptr[c + 1] - d0);
-        if (tile * 64 >= n) continue;
-        const int64_t len = int64_t(n) * nc;
+        const int64_t len = (g.dof_ptr[c + 1] - d0) * nc;
+        const int64_t e = int64_t(item % per) * 256 + threadIdx.x;
+        if (e >= len) continue;
         const int64_t base = d0 * nc;
         const int kuse = w.kuse[c];
         const int depth = w.depth;
         const int head = w.hist[2 * c + 1];
         const cptr<double> gam = (cptr<double>)uni_ptr(w.gamma + int64_t(c) * kMaxDepth);
-
-        const int64_t e0 = int64_t(tile) * 64 * nc;
-        const int64_t e1 = min(len, e0 + int64_t(64) * nc);
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-            double xv = w.gprev[base + e];
-            int j = 0;
-            for (; j + kUpdBatch <= kuse; j += kUpdBatch) {
-                double d[kUpdBatch];
+        double xv = w.gprev[base + e];
+        int j = 0;
+        for (; j + kUpdBatch <= kuse; j += kUpdBatch) {
+            double d[kUpdBatch];
 #pragma unroll
-                for (int u = 0; u < kUpdBatch; ++u)
-                    d[u] = hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j + u) % depth)[e];
+            for (int u = 0; u < kUpdBatch; ++u) d[u] = hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j + u) % depth)[e];
 #pragma unroll
-                for (int u = 0; u < kUpdBatch; ++u) xv -= gam[j + u] * d[u];
-            }
-            for (; j < kuse; ++j) xv -= gam[j] * hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j) % depth)[e];
-            w.x[base + e] = xv;
+            for (int u = 0; u < kUpdBatch; ++u) xv -= gam[j + u] * d[u];
         }
+        for (; j < kuse; ++j) xv -= gam[j] * hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j) % depth)[e];
+        w.x[base + e] = xv;
     }
 }
 
@@ -1719,8 +1747,8 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(k_round_dots<NN>, grid(a.shape.g_dots, tpc), dim3(256), 0, s, a.tab, a.list, a.count, tpc);
         hipLaunchKernelGGL(k_round_solve, grid(a.shape.g_solve, 1), dim3(kWave), 0, s, a.tab, a.list, a.count, a.next,
                            a.next_count);
-        hipLaunchKernelGGL(k_round_update<NN>, grid(a.shape.g_update, tpc), dim3(256), 0, s, a.tab, a.list, a.count,
-                           tpc);
+        hipLaunchKernelGGL(k_round_update<NN>, grid(a.shape.g_update, per), dim3(256), 0, s, a.tab, a.list, a.count,
+                           per);
         return hipGetLastError();
     });
 }
