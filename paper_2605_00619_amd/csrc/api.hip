@@ -332,6 +332,8 @@ afe_status launch_round(Engine &E, int it, const std::vector<int> &upper, int pr
         a.n_upper = upper.empty() ? -1 : upper[gi];
         // every listed cell is at iteration it; graph chunks replay at any it
         a.split = (!gr.mixed && (upper.empty() || it >= afe::kMinvSplitAfter)) ? afe::kMinvSplitK : 1;
+        // short lists (or unknown length): more workgroups per cell in the update
+        a.upd_fine = upper.empty() || int64_t(upper[gi]) * ((gr.max_cell_dofs + 63) / 64) <= afe::kUpdFineTiles;
         a.max_cell_dofs = gr.max_cell_dofs;
         a.max_cell_subtets = gr.max_cell_subtets;
         a.shape = gr.shape;

@@ -151,6 +151,10 @@ hipError_t launch_set_count(int32_t *count, int value, hipStream_t s);
 // kMinvSplitK workgroups per row tile from iteration kMinvSplitAfter on.
 constexpr int kMinvSplitK = 4;
 constexpr int kMinvSplitAfter = 3;
+// The update kernel takes items of 256 values, one per thread, when the list
+// has at most kUpdFineTiles tiles of 64 DOFs (the last iterations: few cells,
+// long histories), else one tile per item.
+constexpr int kUpdFineTiles = 1024;
 
 struct RoundArgs {
     int N, mixed, visc;
@@ -159,6 +163,7 @@ struct RoundArgs {
     int32_t *next, *next_count;
     int n_upper, max_cell_dofs, max_cell_subtets;
     int split;  // M^-1 item split factor: 4 if a listed cell may split its product (tail, or unknown), else 1
+    int upd_fine;    // update items of 256 values (1) or of one 64-DOF tile (0)
     IterShape shape;
     hipEvent_t ev0, ev1;
     unsigned long long *bytes;

@@ -32,24 +32,44 @@ struct Dim {
     static constexpr int threads = spb * npt;
 };
 
-__device__ inline double wave_sum(double v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
-}
-__device__ inline double wave_max(double v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-    return v;
-}
-__device__ inline double wave_min(double v) {
-    for (int o = kWave / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, kWave));
-    return v;
-}
 // v of lane i (i the same in every lane), in every lane
 __device__ inline double lane_bcast(double v, int i) {
     const unsigned long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane(int(unsigned(b)), i);
     const int hi = __builtin_amdgcn_readlane(int(unsigned(b >> 32)), i);
     return __hiloint2double(hi, lo);
+}
+
+// v of another lane of the same row of 16, chosen by a DPP control word
+template <int kCtrl>
+__device__ inline double dpp_f64(double v) {
+    const unsigned long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(unsigned(b)), kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(unsigned(b >> 32)), kCtrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Reduction over the 64 lanes of a wave (every lane active), the same bits in
+// every lane: within each row of 16 by DPP (partner lane xor 1, xor 2, then
+// the mirrored half-row and row, so each step combines two equal-sized
+// disjoint sets and both partners compute the same value), then the four row
+// results taken with readlane and combined in row order.
+template <class Op>
+__device__ inline double wave_reduce(double v, Op op) {
+    v = op(v, dpp_f64<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+    v = op(v, dpp_f64<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+    v = op(v, dpp_f64<0x141>(v));  // row_half_mirror
+    v = op(v, dpp_f64<0x140>(v));  // row_mirror
+    return op(op(op(lane_bcast(v, 0), lane_bcast(v, 16)), lane_bcast(v, 32)), lane_bcast(v, 48));
+}
+__device__ inline double wave_sum(double v) {
+    return wave_reduce(v, [](double a, double b) { return a + b; });
+}
+__device__ inline double wave_max(double v) {
+    return wave_reduce(v, [](double a, double b) { return fmax(a, b); });
+}
+__device__ inline double wave_min(double v) {
+    return wave_reduce(v, [](double a, double b) { return fmin(a, b); });
 }
 
 // Triangular solves of one wave, column by column, with the factor rows in
@@ -1067,7 +1087,7 @@ __global__ void __launch_bounds__(256) k_round_minv32(const DevSlot *__restrict_
 //                  tests convergence, extends (or rebuilds after dropping the
 //                  oldest pairs) the Jacobi-scaled Cholesky factor of the
 //                  Gram matrix of dF, solves for gamma, builds the next list;
-//   k_round_update (item = entry, chunk of 256 values):
+//   k_round_update (item = entry, tile or chunk of 256 values):
 //                  x <- G(x) - sum_j gamma_j dG_j.
 // Difference pairs live in a ring of `depth` slots, logical order oldest
 // first; a column adding no new direction is not appended; when the ring is
@@ -1444,13 +1464,16 @@ __global__ void __launch_bounds__(64) k_round_solve(const DevSlot *__restrict__ 
 
 constexpr int kUpdBatch = 8;
 
-// Work item = (entry, chunk of 256 space-time values of the cell), one value
-// per thread, so a cell's history columns are read by as many waves as it has
-// chunks (in the last iterations few cells are left and each has a long history).
+// Work item = (entry, span of the cell's space-time values): one 64-DOF tile
+// (64 nc values), or with `fine` 256 values, one per thread, so that in the
+// last iterations, with few cells left and long histories, a cell's history
+// columns are read by five times as many waves.  Each value's arithmetic is
+// the same either way.
 template <int N>
 __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
-                                                      const int32_t *__restrict__ count, int per) {
+                                                      const int32_t *__restrict__ count, int per, int fine) {
     constexpr int nc = Dim<N>::nc;
+    const int span = fine ? 256 : 64 * nc;
     const int n_items = *count * per;
     for (int item = xcd_block(); item < n_items; item += gridDim.x) {
         int slot, c;
@@ -1459,24 +1482,28 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
         const DevWork &w = tab[slot].w;
         const int64_t d0 = g.dof_ptr[c];
         const int64_t len = (g.dof_ptr[c + 1] - d0) * nc;
-        const int64_t e = int64_t(item % per) * 256 + threadIdx.x;
-        if (e >= len) continue;
+        const int64_t e0 = int64_t(item % per) * span;
+        if (e0 >= len) continue;
+        const int64_t e1 = min(len, e0 + span);
         const int64_t base = d0 * nc;
         const int kuse = w.kuse[c];
         const int depth = w.depth;
         const int head = w.hist[2 * c + 1];
         const cptr<double> gam = (cptr<double>)uni_ptr(w.gamma + int64_t(c) * kMaxDepth);
-        double xv = w.gprev[base + e];
-        int j = 0;
-        for (; j + kUpdBatch <= kuse; j += kUpdBatch) {
-            double d[kUpdBatch];
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+            double xv = w.gprev[base + e];
+            int j = 0;
+            for (; j + kUpdBatch <= kuse; j += kUpdBatch) {
+                double d[kUpdBatch];
 #pragma unroll
-            for (int u = 0; u < kUpdBatch; ++u) d[u] = hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j + u) % depth)[e];
+                for (int u = 0; u < kUpdBatch; ++u)
+                    d[u] = hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j + u) % depth)[e];
 #pragma unroll
-            for (int u = 0; u < kUpdBatch; ++u) xv -= gam[j + u] * d[u];
+                for (int u = 0; u < kUpdBatch; ++u) xv -= gam[j + u] * d[u];
+            }
+            for (; j < kuse; ++j) xv -= gam[j] * hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j) % depth)[e];
+            w.x[base + e] = xv;
         }
-        for (; j < kuse; ++j) xv -= gam[j] * hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j) % depth)[e];
-        w.x[base + e] = xv;
     }
 }
 
@@ -1747,8 +1774,9 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(k_round_dots<NN>, grid(a.shape.g_dots, tpc), dim3(256), 0, s, a.tab, a.list, a.count, tpc);
         hipLaunchKernelGGL(k_round_solve, grid(a.shape.g_solve, 1), dim3(kWave), 0, s, a.tab, a.list, a.count, a.next,
                            a.next_count);
-        hipLaunchKernelGGL(k_round_update<NN>, grid(a.shape.g_update, per), dim3(256), 0, s, a.tab, a.list, a.count,
-                           per);
+        const int upd_per = a.upd_fine ? per : tpc;
+        hipLaunchKernelGGL(k_round_update<NN>, grid(a.shape.g_update, upd_per), dim3(256), 0, s, a.tab, a.list,
+                           a.count, upd_per, a.upd_fine);
         return hipGetLastError();
     });
 }
