@@ -1120,9 +1120,14 @@ __device__ inline void ring_state(const DevWork &w, int c, int &k, int &head, bo
 // Tiles of 64 DOFs per cell in the partials buffer of a simulation.
 __device__ inline int part_tiles(const DevGrid &g) { return (g.max_cell_dofs + 63) / 64; }
 
+// History columns per pass of the dot products: kDotCols, or kDotColsWide in
+// the instance launched on short lists (fewer passes, each a round trip to
+// memory; more registers, which only the short lists can afford).  Each
+// column's sum is the same either way.
 constexpr int kDotCols = 4;
+constexpr int kDotColsWide = 16;
 
-template <int N>
+template <int N, int DC>
 __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, int tile, double (*accs)[4]) {
     constexpr int nc = Dim<N>::nc, nt = Dim<N>::nt;
     constexpr int kPer = (64 * nc + 255) / 256;  // elements per thread
@@ -1202,29 +1207,29 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
         accs[1][wv] = gmx;
     }
     if (hist_on) {
-        // kDotCols history columns per pass, so that their loads are in flight together
-        for (int j0 = 0; j0 <= k; j0 += kDotCols) {
-            double ph[kDotCols], pb[kDotCols];
+        // DC history columns per pass, so that their loads are in flight together
+        for (int j0 = 0; j0 <= k; j0 += DC) {
+            double ph[DC], pb[DC];
 #pragma unroll
-            for (int u = 0; u < kDotCols; ++u) ph[u] = pb[u] = 0.0;
+            for (int u = 0; u < DC; ++u) ph[u] = pb[u] = 0.0;
 #pragma unroll
             for (int q = 0; q < kPer; ++q) {
                 if (ie[q] < e1) {
-                    double d[kDotCols];
+                    double d[DC];
 #pragma unroll
-                    for (int u = 0; u < kDotCols; ++u) {
+                    for (int u = 0; u < DC; ++u) {
                         const int j = j0 + u;
                         d[u] = j < k ? hist_col(g, w, w.dF, w.dFp, c, base, len, (head + j) % depth)[ie[q]] : dfe[q];
                     }
 #pragma unroll
-                    for (int u = 0; u < kDotCols; ++u) {
+                    for (int u = 0; u < DC; ++u) {
                         ph[u] = fma(d[u], dfe[q], ph[u]);
                         pb[u] = fma(d[u], fe[q], pb[u]);
                     }
                 }
             }
 #pragma unroll
-            for (int u = 0; u < kDotCols; ++u) {
+            for (int u = 0; u < DC; ++u) {
                 const int j = j0 + u;
                 if (j <= k) {
                     const double sh = wave_sum(ph[u]), sb = wave_sum(pb[u]);
@@ -1432,7 +1437,7 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
     __syncthreads();  // Ls is reused by the next item
 }
 
-template <int N>
+template <int N, int DC>
 __global__ void __launch_bounds__(256) k_round_dots(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
                                                     const int32_t *__restrict__ count, int tpc) {
     __shared__ double accs[kPartStride][4];
@@ -1444,7 +1449,7 @@ __global__ void __launch_bounds__(256) k_round_dots(const DevSlot *__restrict__ 
         const DevWork &w = tab[slot].w;
         const int tile = item % tpc;
         if (tile * 64 >= int(g.dof_ptr[c + 1] - g.dof_ptr[c])) continue;
-        and_dots_tile<N>(g, w, c, tile, accs);
+        and_dots_tile<N, DC>(g, w, c, tile, accs);
         __syncthreads();  // accs is rewritten by the next item
     }
 }
@@ -1771,7 +1776,8 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
             hipLaunchKernelGGL(k_round_minv<D::nc>, grid(a.shape.g_minv, tpc * a.split), dim3(256), 0, s, a.tab,
                                a.list, a.count, tpc, a.split, a.bytes);
         if (a.ev1) (void)hipEventRecord(a.ev1, s);
-        hipLaunchKernelGGL(k_round_dots<NN>, grid(a.shape.g_dots, tpc), dim3(256), 0, s, a.tab, a.list, a.count, tpc);
+        auto dots = a.upd_fine && a.n_upper >= 0 ? k_round_dots<NN, kDotColsWide> : k_round_dots<NN, kDotCols>;
+        hipLaunchKernelGGL(dots, grid(a.shape.g_dots, tpc), dim3(256), 0, s, a.tab, a.list, a.count, tpc);
         hipLaunchKernelGGL(k_round_solve, grid(a.shape.g_solve, 1), dim3(kWave), 0, s, a.tab, a.list, a.count, a.next,
                            a.next_count);
         const int upd_per = a.upd_fine ? per : tpc;
@@ -1861,7 +1867,7 @@ IterShape resident_shape(int N, int mixed, int visc) {
         sh.g_gather = fit(reinterpret_cast<const void *>(&k_round_gather<NN>), 256);
         sh.g_minv = mixed ? fit(reinterpret_cast<const void *>(&k_round_minv32<D::nc>), 256)
                           : fit(reinterpret_cast<const void *>(&k_round_minv<D::nc>), 256);
-        sh.g_dots = fit(reinterpret_cast<const void *>(&k_round_dots<NN>), 256);
+        sh.g_dots = fit(reinterpret_cast<const void *>(&k_round_dots<NN, kDotCols>), 256);
         sh.g_solve = fit(reinterpret_cast<const void *>(&k_round_solve), kWave);
         sh.g_update = fit(reinterpret_cast<const void *>(&k_round_update<NN>), 256);
         return hipSuccess;
