@@ -813,15 +813,17 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
     __shared__ double fs[spb][nt][np][15];  // f*, then (once fbar is formed) the physical fluxes F
     __shared__ double fbar[spb][np][15];
     const int tid = threadIdx.x;
+    const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
+    const int64_t k = int64_t(blockIdx.x) * spb + s;
+    const int c = (s < spb) && (k < g.nsub) ? g.sub_cell[k] : -1;
+    const bool valid = c >= 0 && w.late[c] == which;
+    // the later passes have few cells: blocks without one leave before loading anything
+    if (!__syncthreads_or(valid)) return;
     for (int t = tid; t < 3 * np * np; t += blockDim.x) {
         Ks[t] = g.ref->K[t];
         const int d = t / (np * np), mm = (t / np) % np, p = t % np;
         if (VISC) Dt[VISC ? (d * np + p) * np + mm : 0] = g.ref->D[t];
     }
-    const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
-    const int64_t k = int64_t(blockIdx.x) * spb + s;
-    const int c = (s < spb) && (k < g.nsub) ? g.sub_cell[k] : -1;
-    const bool valid = c >= 0 && w.late[c] == which;
     const double dt = *w.dt;
     double G[9], dj = 0.0, mu_c = 0.0;
     double q[5] = {1, 0, 0, 0, 1};
