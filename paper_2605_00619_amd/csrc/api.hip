@@ -730,6 +730,18 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
                     ref.Kfrag[(t * steps + j) * 64 + l] =
                         row < R.np && kk < inner ? R.K[((kk / R.np) * R.np + row) * R.np + kk % R.np] : 0.0;
                 }
+        const int inner4 = 4 * R.np, steps4 = (inner4 + 3) / 4;
+        for (int t = 0; t < tiles; ++t)
+            for (int j = 0; j < steps4; ++j)
+                for (int l = 0; l < 64; ++l) {
+                    const int row = 16 * t + l % 16, kk = 4 * j + l / 16;
+                    double v = 0.0;
+                    if (row < R.np && kk < inner)
+                        v = R.K[((kk / R.np) * R.np + row) * R.np + kk % R.np];
+                    else if (row < R.np && kk < inner4)
+                        v = R.M[row * R.np + kk - inner];
+                    ref.KMfrag[(t * steps4 + j) * 64 + l] = v;
+                }
     }
     for (int a = 0; a < R.nt; ++a) {
         ref.w[a] = R.w[a];

@@ -24,6 +24,9 @@ struct DevRef {
     // (A[i][k] in lane i + 16 k), at (t * steps + j) * 64 + lane with
     // steps = (3 np + 3) / 4
     double Kfrag[2 * 15 * 64];
+    // The same for the mixed-precision contraction, whose inner index has a
+    // fourth block: A[m][3 np + p] = M^[m][p], steps = np
+    double KMfrag[2 * 20 * 64];
 };
 
 struct DevGrid {

@@ -607,11 +607,12 @@ __device__ inline int mf_d_col(int l, int) { return l % 16; }
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // Shape of the chunk's stiffness contraction as one matrix product:
-// rows = node m, inner index = (d, p), columns = (sub-tet, time node, variable).
-template <int N>
+// rows = node m, inner index = (d, p), columns = (sub-tet, time node, variable);
+// in mixed precision a fourth inner block d = 3 carries the mass term.
+template <int N, bool MIXED = false>
 struct Contraction {
     static constexpr int np = Dim<N>::np;
-    static constexpr int inner = 3 * np;
+    static constexpr int inner = (MIXED ? 4 : 3) * np;
     static constexpr int ks = (inner + 3) / 4;  // k-steps of 4
     static constexpr int cols = Dim<N>::spb * Dim<N>::nt * 5;
     static constexpr int ct = (cols + 15) / 16;  // column tiles
@@ -626,24 +627,25 @@ struct Contraction {
 // cores, K^ (rows m, inner (d, p)) times f* (inner (d, p), columns (sub-tet,
 // a, v)), wave w taking column tiles w, w + 4, ...  In mixed precision the
 // sub-tet's part of (K_tau (x) M_i)(q - 1 (x) u^n) is added, which makes rk
-// the unpreconditioned residual of eq:ADER-localCauchy.  Block 0 clears the
-// next list's length.  VISC: some simulation of the group has a physical or
-// artificial viscosity; MIXED: the group's precision.
+// the unpreconditioned residual of eq:ADER-localCauchy: it enters the same
+// product as a fourth inner block, M^ (rows m, inner p) times
+// g_a[p][v] = (1 / w_a) sum_b K_tau[a][b] (q_b - u^n)[p][v].  Block 0 clears
+// the next list's length.  VISC: some simulation of the group has a physical
+// or artificial viscosity; MIXED: the group's precision.
 template <int N, bool VISC, bool MIXED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_round_subtet(const DevSlot *__restrict__ tab,
                                                                    const int32_t *__restrict__ list,
                                                                    const int32_t *__restrict__ count, int chunks,
                                                                    int32_t *next_count) {
-    using C = Contraction<N>;
+    using C = Contraction<N, MIXED>;
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr bool QS = VISC || MIXED;  // nodal states shared through LDS
-    constexpr int nd = VISC ? 3 * np * np : 1, nm = MIXED ? np * np : 1, sm = MIXED ? spb : 1;
+    constexpr int nd = VISC ? 3 * np * np : 1, sm = MIXED ? spb : 1;
     constexpr int qsp = QS ? spb : 1, qnt = QS ? nt : 1, qnp = QS ? np : 1;
     constexpr int mnp = MIXED ? np : 1;
-    __shared__ double fT[4 * C::ks][C::ld];          // B operand: f*_d[s][a][p][v] at (d np + p, (s nt + a) 5 + v)
-    __shared__ double Dt[nd];                        // D^ transposed, as node_flux reads it
-    __shared__ double Mt[nm];
-    __shared__ double qs[qsp][qnt][qnp][5];  // nodal states; in mixed precision then M^ (q_b - u^n)
+    __shared__ double fT[4 * C::ks][C::ld];  // B operand: f*_d[s][a][p][v] at (d np + p, (s nt + a) 5 + v); g at d = 3
+    __shared__ double Dt[nd];                // D^ transposed, as node_flux reads it
+    __shared__ double qs[qsp][qnt][qnp][5];  // nodal states
     __shared__ double us[sm][mnp][5];
     __shared__ double djs[spb];
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
@@ -665,8 +667,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             // the same for every item of the block: the padding of the
             // operands stays zero, the inner index beyond 3 np included
             for (int t = tid; t < 4 * C::ks * C::ld; t += blockDim.x) fT[t / C::ld][t % C::ld] = 0.0;
-            if (MIXED)
-                for (int t = tid; t < np * np; t += blockDim.x) Mt[MIXED ? (t % np) * np + t / np : 0] = g.ref->M[t];
             if (VISC)
                 for (int t = tid; t < 3 * np * np; t += blockDim.x) {
                     const int d = t / (np * np), mm = (t / np) % np, p = t % np;
@@ -698,24 +698,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             node_flux<N, VISC>(Dt, qs[QS ? s : 0][QS ? a : 0], m, G, q, g.gamma, mu_c, dt, fst, F);
             for (int d = 0; d < 3; ++d)
                 for (int v = 0; v < 5; ++v) fT[d * np + m][(s * nt + a) * 5 + v] = fst[d * 5 + v];
-        }
-        if (MIXED) {
-            __syncthreads();
-            // thread (s, b = a, m): the sub-tet mass product of time node b,
-            // stored over the nodal states once every thread has read them
-            double t[5] = {0, 0, 0, 0, 0};
-            if (valid)
-                for (int p = 0; p < np; ++p) {
-                    const double mm = Mt[MIXED ? p * np + m : 0];
-                    for (int v = 0; v < 5; ++v)
-                        t[v] += mm * (qs[QS ? s : 0][QS ? a : 0][QS ? p : 0][v] - us[MIXED ? s : 0][MIXED ? p : 0][v]);
+            if (MIXED) {
+                // g_a at node m: the mass term's inner block
+                const double rw = 1.0 / g.ref->w[a];
+                for (int v = 0; v < 5; ++v) {
+                    double acc = 0.0;
+                    for (int b = 0; b < nt; ++b)
+                        acc += g.ref->Ktau[a * nt + b] *
+                               (qs[QS ? s : 0][QS ? b : 0][QS ? m : 0][v] - us[MIXED ? s : 0][MIXED ? m : 0][v]);
+                    fT[3 * np + m][(s * nt + a) * 5 + v] = rw * acc;
                 }
-            __syncthreads();
-            if (node)
-                for (int v = 0; v < 5; ++v) qs[QS ? s : 0][QS ? a : 0][QS ? m : 0][v] = valid ? t[v] : 0.0;
+            }
         }
         __syncthreads();
-        const gptr<double> Kf = (gptr<double>)uni_ptr(g.ref->Kfrag) + lane;
+        const gptr<double> Kf = (gptr<double>)uni_ptr(MIXED ? g.ref->KMfrag : g.ref->Kfrag) + lane;
         for (int ctile = wv; ctile < C::ct; ctile += 4) {
             dbl4 acc[C::mt];
 #pragma unroll
@@ -737,15 +733,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                     const int ss = col / (nt * 5), aa = (col / 5) % nt, vv = col % 5;
                     const int64_t kk = s0 + int64_t(chunk) * spb + ss;
                     if (kk >= s1) continue;
-                    const double djv = djs[ss];
-                    double val = g.ref->w[aa] * djv * acc[mtile][r];
-                    if (MIXED) {
-                        double mr = 0.0;
-                        for (int b = 0; b < nt; ++b)
-                            mr += g.ref->Ktau[aa * nt + b] * qs[QS ? ss : 0][QS ? b : 0][QS ? row : 0][vv];
-                        val += djv * mr;
-                    }
-                    w.rk[(kk * np + row) * nc + aa * 5 + vv] = val;
+                    w.rk[(kk * np + row) * nc + aa * 5 + vv] = g.ref->w[aa] * djs[ss] * acc[mtile][r];
                 }
         }
         __syncthreads();  // LDS is rewritten by the next item
