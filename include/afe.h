@@ -93,6 +93,10 @@ typedef struct {
                          /* shared pool (memory for large meshes).  The results are   */
                          /* the same bits; a step in which more cells need the pool   */
                          /* fails with AFE_E_HBM_BUDGET.                               */
+    double kappa;        /* heat conduction coefficient: the energy flux carries      */
+                         /* -kappa grad T (Sec. 2); 0 = none, as in the paper's tests */
+    double cv;           /* specific heat at constant volume: T = p / (rho R) with    */
+                         /* R = (gamma - 1) cv (2.5 in the paper's viscous test)      */
 } afe_params;
 
 typedef struct {

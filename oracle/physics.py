@@ -6,9 +6,12 @@ Conserved Q = (rho, rho v, rho E).  Flux tensor columns F_x = (f, g, h):
     energy    v . (rho E I + sigma) - kappa grad T
 with the Stokes stress sigma = (p + 2/3 mu div v) I - mu (grad v + grad v^T)
 and the ideal-gas law p = (gamma - 1)(rho E - rho |v|^2 / 2).
-Heat conduction is neglected (kappa = 0, as in all the paper's tests), so the
-second viscous eigenvalue gamma mu / (Pr rho) vanishes (Pr = mu gamma c_v / kappa
-is infinite) and only 4 mu / (3 rho) remains.
+The temperature is T = p / (rho R) with R = (gamma - 1) c_v, so
+grad T = (grad e - v . grad v) / c_v with e = rho E / rho.  The paper's tests
+neglect heat conduction (kappa = 0, the default here).  With
+Pr = mu gamma c_v / kappa the second viscous eigenvalue gamma mu / (Pr rho) is
+kappa / (c_v rho); the viscous eigenvalue used is the larger of it and
+4 mu / (3 rho).
 
 Arrays carry the 5 conserved variables in the last axis.
 """
@@ -50,11 +53,12 @@ def sound_speed(q: np.ndarray, gamma: float) -> np.ndarray:
     return np.sqrt(gamma * pressure(q, gamma) / q[..., 0])
 
 
-def flux(q: np.ndarray, gamma: float, mu: float = 0.0, grad_q: np.ndarray | None = None) -> np.ndarray:
+def flux(q: np.ndarray, gamma: float, mu: float = 0.0, grad_q: np.ndarray | None = None, kappa: float = 0.0,
+         cv: float = 2.5) -> np.ndarray:
     """Physical flux F[..., x, v] (x = direction, v = conserved variable).
 
     q [..., 5]; grad_q [..., 3, 5] with grad_q[..., x, v] = d q_v / d x_x
-    (needed only when mu != 0).
+    (needed only when mu != 0 or kappa != 0).
     """
     rho = q[..., 0]
     m = q[..., 1:4]
@@ -73,6 +77,13 @@ def flux(q: np.ndarray, gamma: float, mu: float = 0.0, grad_q: np.ndarray | None
     F[..., :, 0] = m
     F[..., :, 1:4] = rho[..., None, None] * v[..., :, None] * v[..., None, :] + sigma
     F[..., :, 4] = v * E[..., None] + (sigma * v[..., :, None]).sum(-2)
+    if kappa != 0.0:
+        # grad T = (grad e - v . grad v) / c_v, e = E / rho
+        e = E / rho
+        ge = (grad_q[..., :, 4] - e[..., None] * grad_q[..., :, 0]) / rho[..., None]
+        gv = (grad_q[..., :, 1:4] - v[..., None, :] * grad_q[..., :, 0:1]) / rho[..., None, None]
+        gT = (ge - (gv * v[..., None, :]).sum(-1)) / cv
+        F[..., :, 4] -= kappa * gT
     return F
 
 
@@ -83,6 +94,6 @@ def max_eig(q: np.ndarray, gamma: float) -> np.ndarray:
     return np.sqrt((vel * vel).sum(-1)) + sound_speed(q, gamma)
 
 
-def visc_eig(q: np.ndarray, mu) -> np.ndarray:
-    """Viscous eigenvalue 4 mu / (3 rho) (the thermal one is zero for kappa = 0)."""
-    return 4.0 * mu / (3.0 * q[..., 0])
+def visc_eig(q: np.ndarray, mu, kappa: float = 0.0, cv: float = 2.5) -> np.ndarray:
+    """Largest viscous eigenvalue: max(4 mu / (3 rho), kappa / (c_v rho))."""
+    return np.maximum(4.0 * mu / (3.0 * q[..., 0]), kappa / (cv * q[..., 0]))

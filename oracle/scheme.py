@@ -28,8 +28,9 @@ R5 (faces, Sec. 4.4): the sum over faces runs over the cell's boundary
    sub-triangles; each integral is 2 A_t Z^ (reference triangle area 1/2).
    In the Rusanov flux "+" is the neighbour and "-" this cell, n outward;
    |lambda_max| is the largest |v.n| + c over the triangle's face nodes on both
-   sides from qbar/dt and |lambda^v_max| the largest 4 mu/(3 rho) likewise with
-   each side's viscosity; one value per sub-triangle.
+   sides from qbar/dt and |lambda^v_max| the largest viscous eigenvalue
+   max(4 mu/(3 rho), kappa/(c_v rho)) likewise with each side's viscosity;
+   one value per sub-triangle.
 R6 (detector, Sec. 4.5): the divergence is the face integral of the velocity
    jump over the cell volume; it enters the flattener multiplied by the cell
    diameter h_i (undivided form) so that it compares with m1 c; c_min is the
@@ -39,9 +40,15 @@ R7 (artificial viscosity, Sec. 4.5, text ends before the formula):
    the cell-mean density and lambda_i the largest nodal |v| + c, i.e. the
    viscosity for which the mesh Reynolds number is one, scaled by beta_i.
 R8 (time step, eqn.timestep): h_i = cell diameter; the max runs over all DOFs
-   with h inside it taken per cell, lambda^v = 4 mu_i / (3 rho).
+   with h inside it taken per cell, lambda^v = max(4 mu_i / (3 rho),
+   kappa / (c_v rho)).
 R9 (initial data): nodal interpolation of the primitive variables, converted
    to conserved variables.
+R15 (heat conduction, Sec. 2): kappa is a constant of the simulation, not
+   raised with the artificial viscosity of R7; T = p / (rho R) with
+   R = (gamma - 1) c_v (c_v a parameter, 2.5 as in the paper's viscous test);
+   the second viscous eigenvalue gamma mu / (Pr rho) with Pr = mu gamma c_v /
+   kappa is kappa / (c_v rho).
 """
 from __future__ import annotations
 
@@ -60,6 +67,8 @@ from .subgrid import build_cells, faces_of_cells
 class Params:
     gamma: float = 1.4
     mu: float = 0.0
+    kappa: float = 0.0  # heat conduction coefficient (R15)
+    cv: float = 2.5     # specific heat at constant volume: R = (gamma - 1) c_v
     m1: float = 0.1
     av: bool = False
     tol: float = 1e-12
@@ -220,7 +229,7 @@ class Oracle:
         for c in self.targets:
             g = self.grids[c]
             uc = self.cell_state(u, c)
-            lam = max_eig(uc, self.p.gamma) + 2.0 * visc_eig(uc, mus[c]) * (2 * N + 1) / g.h
+            lam = max_eig(uc, self.p.gamma) + 2.0 * visc_eig(uc, mus[c], self.p.kappa, self.p.cv) * (2 * N + 1) / g.h
             smax = max(smax, float(lam.max()))
         return cfl * hmin / ((2 * N + 1) * smax)
 
@@ -230,11 +239,11 @@ class Oracle:
         g = self.grids[c]
         qk = q[:, g.conn, :]  # [A, K, P, 5]
         grad = None
-        if mu != 0.0:
+        if mu != 0.0 or self.p.kappa != 0.0:
             # grad q at node m of sub-tet k: sum_d G_k[d, x] (D^_d q_k)_m
             ref_grad = np.einsum("dml,aklv->akmdv", self.ref.D_f, qk)
             grad = np.einsum("kdx,akmdv->akmxv", g.G, ref_grad)
-        return flux(qk, self.p.gamma, mu, grad)
+        return flux(qk, self.p.gamma, mu, grad, self.p.kappa, self.p.cv)
 
     def _contravariant(self, c: int, F: np.ndarray, dt: float) -> np.ndarray:
         """f*_d = dt sum_x G_k[d, x] F_x  (eq:modified_fluxes): [A, K, P, 3, 5]."""
@@ -327,7 +336,8 @@ class Oracle:
         vo = wo[:, 1:4] / wo[:, :1]
         lam = max(float((np.abs(vi @ n) + sound_speed(wi, gam)).max()),
                   float((np.abs(vo @ n) + sound_speed(wo, gam)).max()))
-        lamv = max(float(visc_eig(wi, mus[c]).max()), float(visc_eig(wo, mus[nb]).max()))
+        kap, cv = self.p.kappa, self.p.cv
+        lamv = max(float(visc_eig(wi, mus[c], kap, cv).max()), float(visc_eig(wo, mus[nb], kap, cv).max()))
         eps = (2 * N + 1) / ((g.h + self.grids[nb].h) * math.sqrt(math.pi / 2.0))
         s = lam + 2.0 * eps * lamv
         return 0.5 * np.einsum("jxv,x->jv", Fo + Fi, n) - 0.5 * s * (qo - qi)

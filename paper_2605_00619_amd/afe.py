@@ -57,7 +57,7 @@ class _Params(ctypes.Structure):
         ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("m1", ctypes.c_double), ("av", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double), ("accel_depth", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("hbm_budget", ctypes.c_size_t), ("predictor_guess", ctypes.c_int32),
-        ("history_cells", ctypes.c_int32),
+        ("history_cells", ctypes.c_int32), ("kappa", ctypes.c_double), ("cv", ctypes.c_double),
     ]
 
 
@@ -162,10 +162,13 @@ class Params:
     hbm_budget: int = 0
     predictor_guess: bool = True
     history_cells: int = 0
+    kappa: float = 0.0
+    cv: float = 2.5
 
     def c(self) -> _Params:
         return _Params(self.gamma, self.mu, self.m1, int(self.av), self.max_iter, self.tol, self.accel_depth,
-                       self.precision, self.hbm_budget, int(self.predictor_guess), self.history_cells)
+                       self.precision, self.hbm_budget, int(self.predictor_guess), self.history_cells, self.kappa,
+                       self.cv)
 
 
 @dataclass

@@ -218,7 +218,7 @@ afe_status check_params(const afe_params *p) {
     if (p->history_cells < 0) return fail(AFE_E_ARG, "history_cells must be >= 0");
     if (p->accel_depth < 0 || p->accel_depth > 63) return fail(AFE_E_ARG, "accel_depth must be in [0, 63]");
     if (p->max_iter < 1) return fail(AFE_E_ARG, "max_iter must be >= 1");
-    if (!(p->gamma > 1.0) || p->mu < 0.0 || !(p->tol >= 0.0))
+    if (!(p->gamma > 1.0) || p->mu < 0.0 || !(p->tol >= 0.0) || !(p->kappa >= 0.0) || !(p->cv > 0.0))
         return fail(AFE_E_ARG, "invalid physics or tolerance parameter");
     return AFE_OK;
 }
@@ -251,7 +251,8 @@ afe_status sync_layout(Engine &E, hipStream_t s) {
         E.tab[sl].g = cd->g;
         E.tab[sl].w = cd->w;
         E.tab[sl].w.u = E.u[sl];
-        const int visc = (cd->g.mu != 0.0 || cd->g.av) ? 1 : 0;
+        // 0: inviscid, 1: viscosity, 2: viscosity and heat conduction
+        const int visc = cd->g.kappa != 0.0 ? 2 : (cd->g.mu != 0.0 || cd->g.av) ? 1 : 0;
         const auto key = std::make_tuple(cd->g.N, cd->g.mixed, visc);
         auto it = gid.find(key);
         if (it == gid.end()) {
@@ -674,6 +675,8 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     g.gamma = params->gamma;
     g.mu = params->mu;
     g.m1 = params->m1;
+    g.kappa = params->kappa;
+    g.cv = params->cv;
     g.av = params->av;
     g.mixed = params->precision == AFE_MIXED ? 1 : 0;
     g.guess = params->predictor_guess;

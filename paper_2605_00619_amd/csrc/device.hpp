@@ -35,6 +35,7 @@ struct DevGrid {
     int64_t ndof, nsub;
     int max_cell_dofs, max_cell_subtets;
     double gamma, mu, m1;
+    double kappa, cv;         // heat conduction: energy flux - kappa grad T, T = p / (rho (gamma - 1) cv)
     int av;
     int mixed;                // 1: FP32 preconditioner for the predictor iteration
     int guess;                // 1: predictor start extrapolated from the previous step
@@ -160,7 +161,7 @@ constexpr int kMinvSplitAfter = 3;
 constexpr int kUpdFineTiles = 1024;
 
 struct RoundArgs {
-    int N, mixed, visc;
+    int N, mixed, visc;  // visc: 0 inviscid, 1 viscosity, 2 viscosity and heat conduction
     const DevSlot *tab;
     const int32_t *list, *count;
     int32_t *next, *next_count;

@@ -122,7 +122,9 @@ __device__ __host__ inline int64_t minv_ld(int64_t n) { return (n + 15) & ~int64
 // Physical flux F[x][v] of the compressible Navier-Stokes equations (Sec. 2)
 // at one point.  gq[x][v] = d q_v / d x_x is used only when mu != 0; heat
 // conduction is zero.
-__device__ inline void ns_flux(const double q[5], const double gq[3][5], double gamma, double mu, double F[3][5]) {
+template <bool HEAT>
+__device__ inline void ns_flux(const double q[5], const double gq[3][5], double gamma, double mu, double kappa,
+                               double cv, double F[3][5]) {
     const double rho = q[0];
     const double ir = 1.0 / rho;
     const double v[3] = {q[1] * ir, q[2] * ir, q[3] * ir};
@@ -142,6 +144,22 @@ __device__ inline void ns_flux(const double q[5], const double gq[3][5], double 
         for (int j = 0; j < 3; ++j) F[x][1 + j] = rho * v[x] * v[j] + sig[x][j];
         F[x][4] = v[x] * q[4] + (sig[0][x] * v[0] + sig[1][x] * v[1] + sig[2][x] * v[2]);
     }
+    if (HEAT && kappa != 0.0) {
+        // - kappa grad T, grad T = (grad e - v . grad v) / cv with e = rho E / rho
+        const double e = q[4] * ir;
+        for (int x = 0; x < 3; ++x) {
+            const double ge = (gq[x][4] - e * gq[x][0]) * ir;
+            double vgv = 0.0;
+            for (int j = 0; j < 3; ++j) vgv += v[j] * ((gq[x][1 + j] - v[j] * gq[x][0]) * ir);
+            F[x][4] -= kappa * ((ge - vgv) / cv);
+        }
+    }
+}
+
+// Largest viscous eigenvalue max(4 mu / (3 rho), kappa / (cv rho)): the second
+// is gamma mu / (Pr rho) with Pr = mu gamma cv / kappa.
+__device__ inline double visc_eig(double mu, double kappa, double cv, double rho) {
+    return fmax(4.0 * mu / (3.0 * rho), kappa / (cv * rho));
 }
 
 __device__ inline double pressure5(const double q[5], double gamma) {
@@ -384,7 +402,7 @@ __global__ void __launch_bounds__(256) k_detect(DevGrid g, DevWork w, const doub
         double q[5];
         for (int v = 0; v < 5; ++v) q[v] = u[v * nd + d0 + l];
         const double vv = sqrt(q[1] * q[1] + q[2] * q[2] + q[3] * q[3]) / q[0];
-        const double lv = 4.0 * mu_c / (3.0 * q[0]);
+        const double lv = visc_eig(mu_c, g.kappa, g.cv, q[0]);
         ct = fmax(ct, vv + sqrt(gam * pressure5(q, gam) / q[0]) + 2.0 * lv * double(2 * N + 1) / h);
     }
     ct = wave_max(ct);
@@ -574,13 +592,15 @@ __global__ void k_set_double(double *p, double v) {
 // contravariant form f*_d = dt sum_x G[d][x] F_x (eq:modified_fluxes).  Dt
 // holds D^ transposed, D^_d[m][p] at Dt[(d np + p) np + m], so that the lanes
 // of one sub-tet (consecutive m) read consecutive LDS words.
-template <int N, bool VISC>
+template <int N, int VISC>
 __device__ inline void node_flux(const double *Dt, const double (*qn)[5], int m, const double G[9], const double q[5],
-                                 double gamma, double mu_c, double dt, double *fstar, double F[3][5]) {
+                                 double gamma, double mu_c, double kappa, double cv, double dt, double *fstar,
+                                 double F[3][5]) {
     constexpr int np = Dim<N>::np;
     double gq[3][5] = {};
-    if (!VISC) mu_c = 0.0;  // inviscid group: no cell viscosity
-    if (VISC && mu_c != 0.0) {
+    if (VISC == 0) mu_c = 0.0;  // inviscid group: no cell viscosity
+    if (VISC < 2) kappa = 0.0;  // no heat conduction below level 2
+    if (VISC > 0 && (mu_c != 0.0 || kappa != 0.0)) {
         double rg[3][5] = {};
         for (int d = 0; d < 3; ++d)
             for (int p = 0; p < np; ++p) {
@@ -590,7 +610,7 @@ __device__ inline void node_flux(const double *Dt, const double (*qn)[5], int m,
         for (int x = 0; x < 3; ++x)
             for (int v = 0; v < 5; ++v) gq[x][v] = G[0 * 3 + x] * rg[0][v] + G[1 * 3 + x] * rg[1][v] + G[2 * 3 + x] * rg[2][v];
     }
-    ns_flux(q, gq, gamma, mu_c, F);
+    ns_flux<VISC == 2>(q, gq, gamma, mu_c, kappa, cv, F);
     for (int d = 0; d < 3; ++d)
         for (int v = 0; v < 5; ++v)
             fstar[d * 5 + v] = dt * (G[d * 3 + 0] * F[0][v] + G[d * 3 + 1] * F[1][v] + G[d * 3 + 2] * F[2][v]);
@@ -630,9 +650,11 @@ struct Contraction {
 // the unpreconditioned residual of eq:ADER-localCauchy: it enters the same
 // product as a fourth inner block, M^ (rows m, inner p) times
 // g_a[p][v] = (1 / w_a) sum_b K_tau[a][b] (q_b - u^n)[p][v].  Block 0 clears
-// the next list's length.  VISC: some simulation of the group has a physical
-// or artificial viscosity; MIXED: the group's precision.
-template <int N, bool VISC, bool MIXED>
+// the next list's length.  VISC: 0 inviscid group, 1 some simulation of the
+// group has a physical or artificial viscosity, 2 some has heat conduction as
+// well (the temperature gradient enters the energy flux); MIXED: the group's
+// precision.
+template <int N, int VISC, bool MIXED>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_round_subtet(const DevSlot *__restrict__ tab,
                                                                    const int32_t *__restrict__ list,
                                                                    const int32_t *__restrict__ count, int chunks,
@@ -695,7 +717,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         if (QS) __syncthreads();
         if (valid) {
             double F[3][5], fst[15];
-            node_flux<N, VISC>(Dt, qs[QS ? s : 0][QS ? a : 0], m, G, q, g.gamma, mu_c, dt, fst, F);
+            node_flux<N, VISC>(Dt, qs[QS ? s : 0][QS ? a : 0], m, G, q, g.gamma, mu_c, g.kappa, g.cv, dt, fst, F);
             for (int d = 0; d < 3; ++d)
                 for (int v = 0; v < 5; ++v) fT[d * np + m][(s * nt + a) * 5 + v] = fst[d * 5 + v];
             if (MIXED) {
@@ -791,7 +813,7 @@ __global__ void __launch_bounds__(256) k_round_gather(const DevSlot *__restrict_
 // Time integrals of the converged predictor, all sub-tets of one simulation:
 // the volume term |J| sum_d V^_d F*bar_d (Sec. 4.4) and the face traces
 // (qbar, Fbar) at the boundary-triangle nodes.
-template <int N, bool VISC>
+template <int N, int VISC>
 __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevWork w, int which) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr int nf = Dim<N>::nf;
@@ -827,7 +849,7 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
     }
     __syncthreads();
     double F[3][5];
-    if (valid) node_flux<N, VISC>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, dt, fs[s][a][m], F);
+    if (valid) node_flux<N, VISC>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, g.kappa, g.cv, dt, fs[s][a][m], F);
     __syncthreads();
     if (valid && a == 0) {
         for (int i = 0; i < 15; ++i) {
@@ -1544,7 +1566,7 @@ __global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w, int which) {
         const double li = fabs(vni) + sqrt(gam * pressure5(qi, gam) / qi[0]);
         const double lo = fabs(vno) + sqrt(gam * pressure5(qo, gam) / qo[0]);
         lam_s[t][j] = fmax(li, lo);
-        lamv_s[t][j] = fmax(4.0 * w.mu_cell[ci] / (3.0 * qi[0]), 4.0 * w.mu_cell[co] / (3.0 * qo[0]));
+        lamv_s[t][j] = fmax(visc_eig(w.mu_cell[ci], g.kappa, g.cv, qi[0]), visc_eig(w.mu_cell[co], g.kappa, g.cv, qo[0]));
         eps = double(2 * N + 1) / ((g.h[ci] + g.h[co]) * sqrt(M_PI / 2.0));
         for (int v = 0; v < 5; ++v) {
             const double fsum0 = to[5 + v] + ti[5 + v];
@@ -1752,8 +1774,9 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
             return dim3(unsigned(persistent > 0 ? std::min(persistent, items) : items));
         };
         const int per = int((int64_t(a.max_cell_dofs) * D::nc + 255) / 256);
-        auto sub = a.visc ? (a.mixed ? k_round_subtet<NN, true, true> : k_round_subtet<NN, true, false>)
-                          : (a.mixed ? k_round_subtet<NN, false, true> : k_round_subtet<NN, false, false>);
+        auto sub = a.visc == 2 ? (a.mixed ? k_round_subtet<NN, 2, true> : k_round_subtet<NN, 2, false>)
+                   : a.visc == 1 ? (a.mixed ? k_round_subtet<NN, 1, true> : k_round_subtet<NN, 1, false>)
+                                 : (a.mixed ? k_round_subtet<NN, 0, true> : k_round_subtet<NN, 0, false>);
         hipLaunchKernelGGL(sub, grid(a.shape.g_sub, chunks), dim3(256), 0, s, a.tab, a.list, a.count, chunks,
                            a.next_count);
         hipLaunchKernelGGL(k_round_gather<NN>, grid(a.shape.g_gather, per), dim3(256), 0, s, a.tab, a.list, a.count,
@@ -1808,12 +1831,10 @@ hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, int which, hipSt
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        if (g.mu != 0.0 || g.av)
-            hipLaunchKernelGGL((k_subtet_post<NN, true>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w,
-                               which);
-        else
-            hipLaunchKernelGGL((k_subtet_post<NN, false>), dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g,
-                               w, which);
+        auto post = g.kappa != 0.0              ? k_subtet_post<NN, 2>
+                    : (g.mu != 0.0 || g.av) ? k_subtet_post<NN, 1>
+                                            : k_subtet_post<NN, 0>;
+        hipLaunchKernelGGL(post, dim3(blocks_for(g.nsub, D::spb)), dim3(D::threads), 0, s, g, w, which);
         return hipGetLastError();
     });
 }
@@ -1849,10 +1870,13 @@ IterShape resident_shape(int N, int mixed, int visc) {
     (void)dispatch(N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
-        sh.g_sub = fit(visc ? (mixed ? reinterpret_cast<const void *>(&k_round_subtet<NN, true, true>)
-                                     : reinterpret_cast<const void *>(&k_round_subtet<NN, true, false>))
-                            : (mixed ? reinterpret_cast<const void *>(&k_round_subtet<NN, false, true>)
-                                     : reinterpret_cast<const void *>(&k_round_subtet<NN, false, false>)),
+        const void *subs[3][2] = {{reinterpret_cast<const void *>(&k_round_subtet<NN, 0, false>),
+                                   reinterpret_cast<const void *>(&k_round_subtet<NN, 0, true>)},
+                                  {reinterpret_cast<const void *>(&k_round_subtet<NN, 1, false>),
+                                   reinterpret_cast<const void *>(&k_round_subtet<NN, 1, true>)},
+                                  {reinterpret_cast<const void *>(&k_round_subtet<NN, 2, false>),
+                                   reinterpret_cast<const void *>(&k_round_subtet<NN, 2, true>)}};
+        sh.g_sub = fit(subs[visc < 0 ? 0 : visc > 2 ? 2 : visc][mixed ? 1 : 0],
                        256);
         sh.g_gather = fit(reinterpret_cast<const void *>(&k_round_gather<NN>), 256);
         sh.g_minv = mixed ? fit(reinterpret_cast<const void *>(&k_round_minv32<D::nc>), 256)

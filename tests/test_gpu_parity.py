@@ -182,6 +182,32 @@ def test_step_parity_navier_stokes_taylor_green():
     assert rel_linf(ue, uo) > 1e-9
 
 
+def test_step_parity_heat_conduction(mesh_4):
+    """Navier-Stokes with heat conduction (mu = 1e-4, kappa = 5e-4, c_v = 2.5:
+    Pr = 0.7) on the density wave, whose temperature varies: the temperature
+    gradient enters the nodal energy flux, the time step and the face penalty
+    (viscous eigenvalue kappa / (c_v rho)), one step at N = 2.  As with the
+    artificial viscosity, the stiff diffusion on thin sub-tetrahedra amplifies
+    what the stop test leaves of the predictor error, so the bar is twice the
+    oracle's own spread between two equally valid stops (1e-14 and 1e-14 / 3),
+    and at least 1e-12.  Measured: GPU 8.1e-13 from the oracle, its own spread
+    5.4e-13, the oracle's 4.2e-13; after a second step both grow to ~1e-11."""
+    from oracle.scheme import Oracle, Params
+    afe = _lib()
+    kw = dict(mu=1e-4, kappa=5e-4, cv=2.5)
+    uo, ug, reps, cd, o, dt = _run_both(mesh_4, 2, density_wave, 1, 0.004, Params(**kw), afe.Params(**kw))
+    o3 = Oracle(mesh_4, 2, Params(tol=TOL / 3, max_iter=600, **kw))
+    u3, rep3 = o3.step(o3.initial_state(density_wave), dt)
+    assert rep3.converged
+    spread = rel_linf(u3, uo)
+    print(f"GPU {rel_linf(ug, uo):.2e} from the oracle; oracle spread {spread:.2e}", flush=True)
+    assert spread < 1e-10
+    assert rel_linf(ug, uo) < max(1e-12, 2.0 * spread)
+    # the heat flux does act at this level
+    un, _, _, _, _, _ = _run_both(mesh_4, 2, density_wave, 1, 0.004, Params(mu=1e-4), afe.Params(mu=1e-4), dt=dt)
+    assert rel_linf(un, uo) > 1e-9
+
+
 def test_free_stream_and_conservation_on_gpu(mesh_4):
     from oracle.scheme import Oracle
     afe = _lib()
