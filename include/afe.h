@@ -73,7 +73,9 @@ typedef struct {
     double m1;           /* flattener constant m1 (0.1, Sec. 4.5)                   */
     int32_t av;          /* 1: artificial viscosity from the flattener              */
     int32_t max_iter;    /* predictor iteration cap                                 */
-    double tol;          /* predictor stop: max|G(q)-q| <= tol * max(1, max|G(q)|)  */
+    double tol;          /* predictor stop: max|G(q)-q| <= tol * max(1, max|G(q)|); */
+                         /* tol = 0: every cell takes exactly max_iter applications */
+                         /* of the map (a fixed-sweep mode), which is not a failure */
     int32_t accel_depth; /* Anderson depth m of the predictor iteration (0 = plain)  */
     int32_t precision;   /* AFE_FP64; AFE_MIXED: the predictor iterates with an FP32  */
                          /* Jacobi-scaled copy of M_i^{-1} as preconditioner of the   */
@@ -272,7 +274,10 @@ afe_status afe_batch_detach(afe_batch *b, afe_cell_data *cd);
 
 /* One step of every attached simulation; reps (host, may be NULL) has
  * n_reps entries indexed by slot.  Returns the first failing simulation's
- * status (its state then holds the failed update), AFE_OK if none failed. */
+ * status (its state then holds the failed update), AFE_OK if none failed.
+ * When the call fails before the step completes (AFE_E_ARG, AFE_E_HIP from a
+ * launch, graph capture or allocation), every attached slot's report carries
+ * that status, with zero iteration counts and dt. */
 afe_status afe_batch_step(afe_batch *b, afe_batch_report *reps, int32_t n_reps, void *stream);
 
 afe_status afe_batch_set_shape(afe_batch *b, const afe_launch_shape *shape);

@@ -415,6 +415,10 @@ class Batch:
         out = {k: BatchReport(STATUS_NAMES.get(reps[k].status, str(reps[k].status)), reps[k].iters_min,
                               reps[k].iters_max, reps[k].iters_mean, reps[k].n_troubled, reps[k].status_cell,
                               reps[k].dt) for k in self._members}
+        if code != AFE_OK and all(r.status == "AFE_OK" for r in out.values()):
+            # no member reported the failure: the step did not complete for any of them
+            for r in out.values():
+                r.status = STATUS_NAMES.get(code, str(code))
         if check:
             _check(code)
         return out

@@ -80,6 +80,8 @@ struct Engine {
     bool forked = false;
     // early corrector: the caller steps u in full (not a predictor-only call)
     bool allow_correct = false;
+    // batch_step_on reached the per-slot reports of this call
+    bool reported = false;
     bool forked2 = false;
     hipGraphExec_t g_pre = nullptr, g_post = nullptr, g_chunk[2] = {nullptr, nullptr};
     // profiling of the first group's M^{-1} launches
@@ -582,6 +584,7 @@ afe_status batch_step_on(Engine &E, afe_batch_report *reps, int32_t n_reps, hipS
         HIP_TRY(hipMemcpyAsync(cd->h_scalar + 1, cd->w.dt, sizeof(double), hipMemcpyDeviceToHost, s));
     }
     HIP_TRY(hipStreamSynchronize(s));
+    E.reported = true;
     afe_status first = AFE_OK;
     for (int sl = 0; sl < afe::kMaxSlots; ++sl) {
         afe_cell_data *cd = E.cds[sl];
@@ -1086,10 +1089,22 @@ afe_status afe_batch_step(afe_batch *b, afe_batch_report *reps, int32_t n_reps, 
     if (!b || (reps && n_reps < 0)) return fail(AFE_E_ARG, "invalid argument");
     Engine &E = b->eng;
     if (E.n_slots() == 0) return AFE_OK;
-    return on_own_stream(E, static_cast<hipStream_t>(stream), [&](hipStream_t s) -> afe_status {
+    E.reported = false;
+    const afe_status st = on_own_stream(E, static_cast<hipStream_t>(stream), [&](hipStream_t s) -> afe_status {
         AFE_TRY(sync_layout(E, s));
         return batch_step_on(E, reps, n_reps, s);
     });
+    if (st != AFE_OK && reps && !E.reported) {
+        // the call failed before its per-simulation reports: every attached
+        // simulation carries the call's status (its step did not complete)
+        for (int sl = 0; sl < afe::kMaxSlots && sl < n_reps; ++sl)
+            if (E.cds[sl]) {
+                reps[sl] = afe_batch_report{};
+                reps[sl].status = st;
+                reps[sl].status_cell = -1;
+            }
+    }
+    return st;
 }
 
 afe_status afe_batch_set_shape(afe_batch *b, const afe_launch_shape *shape) {

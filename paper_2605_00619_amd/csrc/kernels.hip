@@ -120,8 +120,8 @@ __device__ inline int xcd_block() {
 __device__ __host__ inline int64_t minv_ld(int64_t n) { return (n + 15) & ~int64_t(15); }
 
 // Physical flux F[x][v] of the compressible Navier-Stokes equations (Sec. 2)
-// at one point.  gq[x][v] = d q_v / d x_x is used only when mu != 0; heat
-// conduction is zero.
+// at one point.  gq[x][v] = d q_v / d x_x feeds the viscous stress when
+// mu != 0 and, with HEAT, the heat flux -kappa grad T when kappa != 0.
 template <bool HEAT>
 __device__ inline void ns_flux(const double q[5], const double gq[3][5], double gamma, double mu, double kappa,
                                double cv, double F[3][5]) {
@@ -1310,7 +1310,7 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
     if (lane == 0) {
         w.iters[c] = it1;
         if (!(conv || last)) next[atomicAdd(next_count, 1)] = entry;
-        if (last && !conv) {
+        if (last && !conv && w.tol > 0.0) {  // tol = 0: exactly max_iter sweeps, not a failure
             atomicOr(&w.status[0], kStatusNoConv);
             atomicMin(&w.status[1], c);
         }

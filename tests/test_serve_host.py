@@ -7,6 +7,7 @@ import threading
 import time
 
 import numpy as np
+import pytest
 
 from paper_2605_00619_amd.serve import Request, Server, summarize
 
@@ -127,3 +128,56 @@ def test_slot_limit_and_rejection_and_failure():
     assert len(be.live) == 0
     # the third request waited for a slot, not for memory
     assert res[2].queue > 0.0
+
+
+class _FailingLib:
+    """Stand-in for libafe whose batch step fails before it fills any report
+    (as a HIP launch or allocation failure does)."""
+
+    def afe_batch_step(self, h, reps, n, stream):
+        return -7
+
+    def afe_last_error(self):
+        return b"launch failed"
+
+
+def test_call_failure_marks_every_served_request_failed(monkeypatch):
+    """A batch step that fails as a call (AFE_E_HIP) leaves the reports
+    unfilled; the binding gives every member the call's status, so the server
+    retires the requests as failed instead of counting a step that never ran."""
+    import types
+
+    from paper_2605_00619_amd import afe
+    from paper_2605_00619_amd.serve import GpuBackend
+
+    monkeypatch.setattr(afe, "_lib", _FailingLib())
+    batch = object.__new__(afe.Batch)
+    batch._h = None
+    batch._members = {}
+    reps = batch.step(stream=0, check=False)
+    assert reps == {}
+
+    class Backend(FakeBackend):
+        def attach(self, req, _):
+            slot = super().attach(req, _)
+            batch._members[slot] = (None, None)
+            return slot
+
+        def step(self):
+            return GpuBackend.step(self)
+
+        def release(self, req, keep):
+            slot = [s for s, (r, _) in self.live.items() if r is req][0]
+            del batch._members[slot]
+            return super().release(req, keep)
+
+    clock = Clock()
+    be = Backend(clock, 100)
+    be.batch = batch
+    be.step_stream = types.SimpleNamespace(cuda_stream=0)
+    res = Server(be, 100, clock=clock, sleep=clock.advance).run([_req(0, 0.0, 10, 5), _req(1, 0.0, 10, 5)])
+    assert [r.status for r in res] == ["AFE_E_HIP", "AFE_E_HIP"]
+    assert [r.steps_done for r in res] == [1, 1]
+    assert summarize(res)["completed"] == 0
+    with pytest.raises(afe.AfeError):
+        batch.step(stream=0, check=True)
