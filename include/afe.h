@@ -200,12 +200,17 @@ afe_status afe_cell_diagnostics(const afe_cell_data *cd, int32_t *iters, double 
 
 /* Timing of the dominant kernel (the M_i^{-1} application of the predictor
  * iteration, Sec. 4.3 eq:ader4): when enabled, HIP events bracket each of its
- * launches on the object's stream and the kernel counts the algorithmic bytes
- * it moves (8 N_i^2 of M_i^{-1} plus the space-time blocks read and written,
- * 16 N_i 5(N+1), per cell and iteration).  afe_profile_read returns the sums
- * since the last enable. */
+ * launches on the object's stream and the kernel counts the bytes it moves.
+ * afe_profile_read returns the sums since the last enable: *bytes the
+ * algorithmic bytes, per cell and iteration the packed symmetric M_i^{-1}
+ * (N_i (N_i + 1) / 2 entries: 8 bytes each in FP64, 4 in the mixed-precision
+ * FP32 copy) plus the space-time block read and the result written once
+ * (16 N_i 5(N+1) in FP64; 12 N_i 5(N+1) in mixed precision, FP32 in and FP64
+ * out); *bytes_stored the bytes of the layout as stored and streamed.  Any
+ * output pointer may be NULL. */
 afe_status afe_profile_enable(afe_cell_data *cd, int32_t enable);
-afe_status afe_profile_read(afe_cell_data *cd, double *kernel_ms, int64_t *launches, double *bytes);
+afe_status afe_profile_read(afe_cell_data *cd, double *kernel_ms, int64_t *launches, double *bytes,
+                            double *bytes_stored);
 
 void afe_free(afe_cell_data *cd);
 const char *afe_last_error(void);
@@ -293,7 +298,8 @@ afe_status afe_batch_tune(afe_batch *b, void *stream, afe_launch_shape *chosen);
 /* As afe_profile_enable / afe_profile_read for the batch's M_i^{-1} launches
  * of its first group of simulations (graph replay is off while enabled). */
 afe_status afe_batch_profile_enable(afe_batch *b, int32_t enable);
-afe_status afe_batch_profile_read(afe_batch *b, double *kernel_ms, int64_t *launches, double *bytes);
+afe_status afe_batch_profile_read(afe_batch *b, double *kernel_ms, int64_t *launches, double *bytes,
+                                  double *bytes_stored);
 
 #ifdef __cplusplus
 }

@@ -121,7 +121,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afe_subgrid_host": ([ctypes.POINTER(_Mesh), i32, vp, vp, vp, vp, vp, vp, vp], i32),
         "afe_last_error": ([], ctypes.c_char_p),
         "afe_profile_enable": ([vp, i32], i32),
-        "afe_profile_read": ([vp, vp, vp, vp], i32),
+        "afe_profile_read": ([vp, vp, vp, vp, vp], i32),
         "afe_estimate_bytes": ([ctypes.POINTER(_Mesh), i32, ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_size_t)],
                                i32),
         "afe_batch_create": ([ctypes.POINTER(vp)], i32),
@@ -133,7 +133,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afe_batch_get_shape": ([vp, ctypes.POINTER(_Shape)], i32),
         "afe_batch_tune": ([vp, vp, ctypes.POINTER(_Shape)], i32),
         "afe_batch_profile_enable": ([vp, i32], i32),
-        "afe_batch_profile_read": ([vp, vp, vp, vp], i32),
+        "afe_batch_profile_read": ([vp, vp, vp, vp, vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -329,12 +329,14 @@ class CellData:
         _check(_lib.afe_profile_enable(self._h, int(on)))
 
     def profile_read(self):
-        """(milliseconds, launches, algorithmic bytes) of the predictor's M^-1 kernel."""
+        """(milliseconds, launches, algorithmic bytes, bytes as stored) of the
+        predictor's M^-1 kernel."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         b = ctypes.c_double()
-        _check(_lib.afe_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
-        return float(ms.value), int(n.value), float(b.value)
+        bs = ctypes.c_double()
+        _check(_lib.afe_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b), ctypes.byref(bs)))
+        return float(ms.value), int(n.value), float(b.value), float(bs.value)
 
     def diagnostics(self, stream=None):
         it = np.zeros(self.n_cells, dtype=np.int32)
@@ -443,8 +445,12 @@ class Batch:
         _check(_lib.afe_batch_profile_enable(self._h, int(on)))
 
     def profile_read(self):
+        """(milliseconds, launches, algorithmic bytes, bytes as stored) of the
+        predictor's M^-1 kernel of the first group."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
         b = ctypes.c_double()
-        _check(_lib.afe_batch_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
-        return float(ms.value), int(n.value), float(b.value)
+        bs = ctypes.c_double()
+        _check(_lib.afe_batch_profile_read(self._h, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b),
+                                           ctypes.byref(bs)))
+        return float(ms.value), int(n.value), float(b.value), float(bs.value)

@@ -520,21 +520,22 @@ afe_status profile_enable(Engine &E, int32_t enable) {
             HIP_TRY(hipEventCreate(&E.hooks.start[i]));
             HIP_TRY(hipEventCreate(&E.hooks.stop[i]));
         }
-        HIP_TRY(hipMalloc(&E.d_bytes, sizeof(unsigned long long)));
+        HIP_TRY(hipMalloc(&E.d_bytes, 2 * sizeof(unsigned long long)));
     }
     E.prof_on = enable != 0;
     E.prof_ms = 0.0;
     E.prof_launches = 0;
-    if (E.d_bytes) HIP_TRY(hipMemset(E.d_bytes, 0, sizeof(unsigned long long)));
+    if (E.d_bytes) HIP_TRY(hipMemset(E.d_bytes, 0, 2 * sizeof(unsigned long long)));
     return AFE_OK;
 }
 
-afe_status profile_read(Engine &E, double *kernel_ms, int64_t *launches, double *bytes) {
-    unsigned long long b = 0;
-    if (E.d_bytes) HIP_TRY(hipMemcpy(&b, E.d_bytes, sizeof(b), hipMemcpyDeviceToHost));
+afe_status profile_read(Engine &E, double *kernel_ms, int64_t *launches, double *bytes, double *bytes_stored) {
+    unsigned long long b[2] = {0, 0};
+    if (E.d_bytes) HIP_TRY(hipMemcpy(b, E.d_bytes, sizeof(b), hipMemcpyDeviceToHost));
     if (kernel_ms) *kernel_ms = E.prof_ms;
     if (launches) *launches = E.prof_launches;
-    if (bytes) *bytes = double(b);
+    if (bytes) *bytes = double(b[0]);
+    if (bytes_stored) *bytes_stored = double(b[1]);
     return AFE_OK;
 }
 
@@ -1018,9 +1019,10 @@ afe_status afe_profile_enable(afe_cell_data *cd, int32_t enable) {
     return profile_enable(cd->solo, enable);
 }
 
-afe_status afe_profile_read(afe_cell_data *cd, double *kernel_ms, int64_t *launches, double *bytes) {
+afe_status afe_profile_read(afe_cell_data *cd, double *kernel_ms, int64_t *launches, double *bytes,
+                            double *bytes_stored) {
     if (!cd) return fail(AFE_E_ARG, "null argument");
-    return profile_read(cd->solo, kernel_ms, launches, bytes);
+    return profile_read(cd->solo, kernel_ms, launches, bytes, bytes_stored);
 }
 
 afe_status afe_predictor_state(const afe_cell_data *cd, double *q, void *stream) {
@@ -1241,9 +1243,10 @@ afe_status afe_batch_profile_enable(afe_batch *b, int32_t enable) {
     return profile_enable(b->eng, enable);
 }
 
-afe_status afe_batch_profile_read(afe_batch *b, double *kernel_ms, int64_t *launches, double *bytes) {
+afe_status afe_batch_profile_read(afe_batch *b, double *kernel_ms, int64_t *launches, double *bytes,
+                                  double *bytes_stored) {
     if (!b) return fail(AFE_E_ARG, "null argument");
-    return profile_read(b->eng, kernel_ms, launches, bytes);
+    return profile_read(b->eng, kernel_ms, launches, bytes, bytes_stored);
 }
 
 }  // extern "C"

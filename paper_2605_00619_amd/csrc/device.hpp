@@ -126,7 +126,9 @@ struct IterShape {
 };
 
 // Events bracketing each launch of the predictor's M^{-1} kernel, and its
-// algorithmic byte counter.
+// byte counters: [0] algorithmic bytes (the packed triangle of M_i^{-1},
+// n_i (n_i + 1) / 2 entries, plus the right-hand side read and the result
+// written once, per cell and iteration), [1] bytes as stored and streamed.
 constexpr int kMaxRounds = 16;
 struct ProfileHooks {
     hipEvent_t start[kMaxRounds], stop[kMaxRounds];
@@ -170,7 +172,7 @@ struct RoundArgs {
     int upd_fine;    // update items of 256 values (1) or of one 64-DOF tile (0)
     IterShape shape;
     hipEvent_t ev0, ev1;
-    unsigned long long *bytes;
+    unsigned long long *bytes;  // [2] algorithmic, as stored (see ProfileHooks); null: not counted
 };
 hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s);
 // Early passes over cells whose predictor is final while others still

@@ -920,9 +920,14 @@ __device__ inline void minv_tile(const DevGrid &g, int c, int tile, int jb, int 
     const int r0 = tile * kWave;
     if (r0 >= n) return;
     if (bytes != nullptr && threadIdx.x == 0) {
-        // matrix and right-hand side once over the splits, the result once per row
+        // as stored: matrix and right-hand side once over the splits, the result once per row
         const unsigned long long rows = unsigned(min(kWave, n - r0)), w = unsigned(je - jb);
-        atomicAdd(bytes, 8ull * (rows * w + (jb == 0 ? rows * NC : 0u) + (tile == 0 ? w * NC : 0u)));
+        atomicAdd(bytes + 1, 8ull * (rows * w + (jb == 0 ? rows * NC : 0u) + (tile == 0 ? w * NC : 0u)));
+        // algorithmic, once per cell: the packed triangle, the right-hand side and the result
+        if (tile == 0 && jb == 0) {
+            const unsigned long long nn = unsigned(n);
+            atomicAdd(bytes, 4ull * nn * (nn + 1) + 16ull * nn * NC);
+        }
     }
     const int row = r0 + lane;
     const bool ok = row < n;
@@ -1036,8 +1041,14 @@ __global__ void __launch_bounds__(256) k_round_minv32(const DevSlot *__restrict_
         const int r0 = tile * kWave;
         if (r0 >= n) continue;
         if (bytes != nullptr && threadIdx.x == 0) {
+            // as stored: FP32 rows, FP64 result, FP32 right-hand side once
             const unsigned long long rows = unsigned(min(kWave, n - r0));
-            atomicAdd(bytes, 4ull * rows * unsigned(n) + 8ull * rows * NC + (tile == 0 ? 4ull * unsigned(n) * NC : 0ull));
+            atomicAdd(bytes + 1, 4ull * rows * unsigned(n) + 8ull * rows * NC + (tile == 0 ? 4ull * unsigned(n) * NC : 0ull));
+            // algorithmic, once per cell: the packed FP32 triangle, FP32 right-hand side, FP64 result
+            if (tile == 0) {
+                const unsigned long long nn = unsigned(n);
+                atomicAdd(bytes, 2ull * nn * (nn + 1) + 12ull * nn * NC);
+            }
         }
         const int row = r0 + lane;
         const bool ok = row < n;
