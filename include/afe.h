@@ -212,6 +212,24 @@ afe_status afe_profile_enable(afe_cell_data *cd, int32_t enable);
 afe_status afe_profile_read(afe_cell_data *cd, double *kernel_ms, int64_t *launches, double *bytes,
                             double *bytes_stored);
 
+/* Error norm of Sec. 5: ||e||_2 = (sum over cells of int_cell |u_h - u_e|^2)^(1/2)
+ * for one conserved variable (var 0..4), each cell integral taken over its
+ * sub-tets with a conical product of (N+3)-point Gauss-Legendre rules
+ * (nq = (N+3)^3 points per sub-tet, exact for polynomials of degree 2N+3).
+ * afe_l2_points writes *nq (host) and, when xq is not NULL, the points' physical
+ * coordinates in each cell's frame, xq device [n_subtets * nq][3] (sub-tet
+ * major), from the DOF coordinates dof_xyz device [3][ndof] of afe_dof_coords;
+ * the caller evaluates u_e there (points may lie outside [0, box): a periodic
+ * u_e wraps them).  afe_l2_error takes those values, ref device
+ * [n_subtets * nq] (a NaN leaves its point out of the sum: the norm over a
+ * part of the domain), and the state u device [5][ndof], and returns the norm in
+ * *err (host); the sum is in a fixed order (bit-reproducible).  It uses the
+ * object's work buffers: not concurrently with a step of the same object.
+ * Synchronises `stream`.  Errors: AFE_E_ARG, AFE_E_HIP. */
+afe_status afe_l2_points(afe_cell_data *cd, const double *dof_xyz, double *xq, int32_t *nq, void *stream);
+afe_status afe_l2_error(afe_cell_data *cd, const double *u, int32_t var, const double *ref, double *err,
+                        void *stream);
+
 void afe_free(afe_cell_data *cd);
 const char *afe_last_error(void);
 

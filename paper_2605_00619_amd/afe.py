@@ -31,7 +31,7 @@ EXPORTED = [
     "afe_subgrid_host", "afe_profile_enable", "afe_profile_read", "afe_estimate_bytes",
     "afe_batch_create", "afe_batch_free", "afe_batch_attach", "afe_batch_detach", "afe_batch_step",
     "afe_batch_set_shape", "afe_batch_get_shape", "afe_batch_tune", "afe_batch_profile_enable",
-    "afe_batch_profile_read",
+    "afe_batch_profile_read", "afe_l2_points", "afe_l2_error",
 ]
 BATCH_SLOTS = 64
 
@@ -117,6 +117,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afe_predictor_state": ([vp, vp, vp], i32),
         "afe_cell_diagnostics": ([vp, vp, vp, vp], i32),
         "afe_free": ([vp], None),
+        "afe_l2_points": ([vp, vp, vp, ctypes.POINTER(i32), vp], i32),
+        "afe_l2_error": ([vp, vp, i32, vp, ctypes.POINTER(dbl), vp], i32),
         "afe_subgrid_sizes": ([ctypes.POINTER(_Mesh), i32, vp], i32),
         "afe_subgrid_host": ([ctypes.POINTER(_Mesh), i32, vp, vp, vp, vp, vp, vp, vp], i32),
         "afe_last_error": ([], ctypes.c_char_p),
@@ -318,6 +320,24 @@ class CellData:
         if not report:
             return None
         return StepReport(rep.iters_min, rep.iters_max, rep.iters_mean, rep.n_troubled, rep.status_cell)
+
+    def l2_points(self, stream=None):
+        """Error-norm quadrature points [n_subtets * nq, 3] (device), each
+        cell's frame; nq = (N + 3)^3 points per sub-tet."""
+        import torch
+        nq = ctypes.c_int32()
+        _check(_lib.afe_l2_points(self._h, None, None, ctypes.byref(nq), _stream(stream)))
+        x = self.dof_coords(stream)
+        xq = torch.empty((self.n_subtets * nq.value, 3), dtype=torch.float64, device="cuda")
+        _check(_lib.afe_l2_points(self._h, _dev(x), _dev(xq), ctypes.byref(nq), _stream(stream)))
+        return xq
+
+    def l2_error(self, u, var: int, ref, stream=None) -> float:
+        """(sum over cells of int |u_h[var] - u_e|^2)^(1/2) with ref = u_e at
+        the points of l2_points (device, [n_subtets * nq])."""
+        out = ctypes.c_double()
+        _check(_lib.afe_l2_error(self._h, _dev(u), int(var), _dev(ref), ctypes.byref(out), _stream(stream)))
+        return float(out.value)
 
     def predictor_state(self, stream=None):
         import torch

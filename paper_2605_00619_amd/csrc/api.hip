@@ -754,6 +754,12 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         ref.w[a] = R.w[a];
         ref.tau[a] = R.tau[a];
     }
+    ref.nq = R.nq;
+    for (int q = 0; q < R.nq; ++q) {
+        for (int x = 0; x < 3; ++x) ref.qxi[3 * q + x] = R.qxi[3 * q + x];
+        ref.qw[q] = R.qw[q];
+        for (int m = 0; m < R.np; ++m) ref.qphi[q * R.np + m] = R.qphi[q * R.np + m];
+    }
     for (int i = 0; i < R.nt * R.nt; ++i) {
         ref.Ktau_inv[i] = R.Ktau_inv[i];
         ref.Ktau[i] = R.Ktau[i];
@@ -1011,6 +1017,31 @@ afe_status ader_step(afe_cell_data *cd, double *u, double dt, afe_step_report *r
     }
     const afe_status st = status_of(h[0]);
     if (st != AFE_OK) return fail(st, status_text(st));
+    return AFE_OK;
+}
+
+afe_status afe_l2_points(afe_cell_data *cd, const double *dof_xyz, double *xq, int32_t *nq, void *stream) {
+    if (!cd) return fail(AFE_E_ARG, "null argument");
+    const afe::RefData &R = afe::ref_data(cd->host.N);
+    if (nq) *nq = R.nq;
+    if (!xq) return AFE_OK;
+    if (!dof_xyz) return fail(AFE_E_ARG, "null DOF coordinates");
+    HIP_TRY(afe::launch_l2_points(cd->g, dof_xyz, xq, static_cast<hipStream_t>(stream)));
+    return AFE_OK;
+}
+
+afe_status afe_l2_error(afe_cell_data *cd, const double *u, int32_t var, const double *ref, double *err,
+                        void *stream) {
+    if (!cd || !u || !ref || !err) return fail(AFE_E_ARG, "null argument");
+    if (var < 0 || var > 4) return fail(AFE_E_ARG, "var must be in [0, 4]");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // the partial sums use the object's Anderson partials buffer (free between steps)
+    const int64_t cap = int64_t(cd->host.n_cells) * ((cd->host.max_cell_dofs + 63) / 64) * 130;
+    if (afe::l2_blocks(cd->g) > cap) return fail(AFE_E_ARG, "error-norm partials exceed the work buffer");
+    HIP_TRY(afe::launch_l2_error(cd->g, u, var, ref, cd->w.part, cd->d_scalar, s));
+    HIP_TRY(hipMemcpyAsync(cd->h_scalar, cd->d_scalar, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *err = std::sqrt(cd->h_scalar[0]);
     return AFE_OK;
 }
 

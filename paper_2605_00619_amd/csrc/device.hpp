@@ -27,6 +27,12 @@ struct DevRef {
     // The same for the mixed-precision contraction, whose inner index has a
     // fourth block: A[m][3 np + p] = M^[m][p], steps = np
     double KMfrag[2 * 20 * 64];
+    // volume quadrature of the error norms: points, weights (sum 1/6) and
+    // basis values phi_m(xi_q) at [q * np + m]
+    int nq;
+    double qxi[216 * 3];
+    double qw[216];
+    double qphi[216 * 20];
 };
 
 struct DevGrid {
@@ -195,6 +201,14 @@ hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, int which, hipSt
 hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, int which, hipStream_t s);
 // Predictor iteration counts of the step into status[4..7].
 hipError_t launch_step_stats(const DevGrid &g, const DevWork &w, hipStream_t s);
+// Physical coordinates of the error-norm quadrature points of every sub-tet,
+// xq [nsub * nq][3], from the DOF coordinates dof_xyz [3][ndof].
+hipError_t launch_l2_points(const DevGrid &g, const double *dof_xyz, double *xq, hipStream_t s);
+// sum over sub-tets and points of w_q |det J| (u_h[var](x_q) - ref_q)^2 into
+// *out (device), deterministic; partial [blocks] is scratch.
+hipError_t launch_l2_error(const DevGrid &g, const double *u, int var, const double *ref, double *partial,
+                           double *out, hipStream_t s);
+int64_t l2_blocks(const DevGrid &g);
 // Occupancy-derived persistent grid sizes for degree N, precision and
 // viscosity (workgroups that fit on the device at once, per kernel).
 IterShape resident_shape(int N, int mixed, int visc);

@@ -1701,6 +1701,75 @@ __global__ void k_positivity(DevGrid g, DevWork w, const double *__restrict__ u,
     }
 }
 
+// ------------------------------------------------------- error norms
+//
+// The L2 norm of Sec. 5, (sum over cells of int |u_h - u_e|^2)^(1/2), with
+// each cell's integral taken over its sub-tets by the conical product rule of
+// the reference data: thread = (sub-tet k, point q).  The vertices of sub-tet
+// k are its reference nodes 0..3 (the App. A order), so the point is
+// X0 + sum_d xi_d (X_d - X0) with X the DOF coordinates of those nodes.
+
+constexpr int kL2Threads = 256;
+
+__global__ void __launch_bounds__(kL2Threads) k_l2_points(DevGrid g, const double *__restrict__ dof_xyz,
+                                                         double *__restrict__ xq) {
+    const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int nq = g.ref->nq;
+    if (t >= g.nsub * nq) return;
+    const int64_t k = t / nq;
+    const int q = int(t % nq);
+    const int64_t d0 = g.dof_ptr[g.sub_cell[k]];
+    double X[4][3];
+    for (int v = 0; v < 4; ++v) {
+        const int64_t l = d0 + g.conn[k * g.np + v];
+        for (int x = 0; x < 3; ++x) X[v][x] = dof_xyz[x * g.ndof + l];
+    }
+    const double *xi = g.ref->qxi + 3 * q;
+    for (int x = 0; x < 3; ++x)
+        xq[t * 3 + x] = X[0][x] + xi[0] * (X[1][x] - X[0][x]) + xi[1] * (X[2][x] - X[0][x]) + xi[2] * (X[3][x] - X[0][x]);
+}
+
+// Block b sums its 256 terms in a fixed tree order into partial[b].
+__global__ void __launch_bounds__(kL2Threads) k_l2_terms(DevGrid g, const double *__restrict__ u, int var,
+                                                        const double *__restrict__ ref, double *__restrict__ partial) {
+    __shared__ double red[kL2Threads];
+    const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    const int nq = g.ref->nq, np = g.np;
+    double e = 0.0;
+    if (t < g.nsub * nq) {
+        const int64_t k = t / nq;
+        const int q = int(t % nq);
+        const int64_t d0 = g.dof_ptr[g.sub_cell[k]];
+        const double *ph = g.ref->qphi + q * np;
+        double uh = 0.0;
+        for (int m = 0; m < np; ++m) uh += ph[m] * u[var * g.ndof + d0 + g.conn[k * np + m]];
+        const double r = ref[t];
+        const double d = uh - r;
+        e = r == r ? g.ref->qw[q] * g.geo[k * 10 + 9] * d * d : 0.0;  // NaN: point left out
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int h = kL2Threads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// One block: the partials in a fixed order (each thread a strided sum, then a tree).
+__global__ void __launch_bounds__(kL2Threads) k_l2_sum(const double *__restrict__ partial, int64_t n, double *out) {
+    __shared__ double red[kL2Threads];
+    double a = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) a += partial[i];
+    red[threadIdx.x] = a;
+    __syncthreads();
+    for (int h = kL2Threads / 2; h > 0; h >>= 1) {
+        if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0];
+}
+
 template <typename F>
 hipError_t dispatch(int N, F &&f) {
     switch (N) {
@@ -1866,6 +1935,21 @@ hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, int whi
 
 hipError_t launch_step_stats(const DevGrid &g, const DevWork &w, hipStream_t s) {
     hipLaunchKernelGGL(k_step_stats, dim3(1), dim3(1024), 0, s, w, g.n_cells);
+    return hipGetLastError();
+}
+
+int64_t l2_blocks(const DevGrid &g) { return (g.nsub * int64_t((g.N + 3) * (g.N + 3) * (g.N + 3)) + kL2Threads - 1) / kL2Threads; }
+
+hipError_t launch_l2_points(const DevGrid &g, const double *dof_xyz, double *xq, hipStream_t s) {
+    hipLaunchKernelGGL(k_l2_points, dim3(unsigned(l2_blocks(g))), dim3(kL2Threads), 0, s, g, dof_xyz, xq);
+    return hipGetLastError();
+}
+
+hipError_t launch_l2_error(const DevGrid &g, const double *u, int var, const double *ref, double *partial,
+                           double *out, hipStream_t s) {
+    const int64_t nb = l2_blocks(g);
+    hipLaunchKernelGGL(k_l2_terms, dim3(unsigned(nb)), dim3(kL2Threads), 0, s, g, u, var, ref, partial);
+    hipLaunchKernelGGL(k_l2_sum, dim3(1), dim3(kL2Threads), 0, s, partial, nb, out);
     return hipGetLastError();
 }
 

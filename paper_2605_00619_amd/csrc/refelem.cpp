@@ -302,6 +302,34 @@ RefData build(int N) {
             R.Ktau[a * nt + b] = psi(a, 1.0) * psi(b, 1.0) - integ;
         }
     invert_small(R.Ktau, R.Ktau_inv, nt);
+    // conical product rule for error norms: n-point Gauss-Legendre on [0, 1]
+    // in each collapsed coordinate, n = N + 3
+    const int ng = N + 3;
+    std::vector<double> gx(ng), gw(ng);
+    for (int i = 0; i < ng; ++i) {
+        double x = std::cos(M_PI * (i + 0.75) / (ng + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p, dp;
+            legendre(ng, x, p, dp);
+            const double dx = p / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-17) break;
+        }
+        double p, dp;
+        legendre(ng, x, p, dp);
+        gx[i] = 0.5 * (x + 1.0);
+        gw[i] = 1.0 / ((1.0 - x * x) * dp * dp);
+    }
+    R.nq = ng * ng * ng;
+    for (int ia = 0; ia < ng; ++ia)
+        for (int ib = 0; ib < ng; ++ib)
+            for (int ic = 0; ic < ng; ++ic) {
+                const double a = gx[ia], b = gx[ib], c = gx[ic];
+                const double xi[3] = {a * (1.0 - b) * (1.0 - c), b * (1.0 - c), c};
+                R.qxi.insert(R.qxi.end(), xi, xi + 3);
+                R.qw.push_back(gw[ia] * gw[ib] * gw[ic] * (1.0 - b) * (1.0 - c) * (1.0 - c));
+                for (int m = 0; m < R.np; ++m) R.qphi.push_back(phi[m].eval(xi[0], xi[1], xi[2]));
+            }
     return R;
 }
 

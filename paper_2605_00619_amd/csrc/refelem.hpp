@@ -25,7 +25,16 @@ struct RefData {
     // time basis on [0, 1]
     std::vector<double> tau, w;             // Gauss-Legendre nodes and weights
     std::vector<double> Ktau, Ktau_inv;     // [nt][nt]
+    // volume quadrature for error norms: conical product of (N + 3)-point
+    // Gauss-Legendre rules, xi = (a (1-b)(1-c), b (1-c), c), weight
+    // w_a w_b w_c (1-b)(1-c)^2; exact for polynomials of degree 2N + 3
+    int nq = 0;
+    std::vector<double> qxi;                // [nq][3]
+    std::vector<double> qw;                 // [nq], sum 1/6
+    std::vector<double> qphi;               // [nq][np] phi_m(xi_q)
 };
+
+constexpr int kMaxNq = (kMaxN + 3) * (kMaxN + 3) * (kMaxN + 3);
 
 // Builds the exact reference data for 1 <= N <= 3 (cached).
 const RefData &ref_data(int N);
