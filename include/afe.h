@@ -189,6 +189,22 @@ afe_status ader_correct(afe_cell_data *cd, double *u, double dt, void *stream);
  * step failed (u then holds the failed update). */
 afe_status ader_step(afe_cell_data *cd, double *u, double dt, afe_step_report *rep, void *stream);
 
+/* ader_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same step, the same kernels and the same result, but nothing is allocated
+ * (no hipMalloc, hipFree or host-pinned allocation; ader_step allocates its
+ * predictor lists on first use and again whenever it is handed another
+ * state).  The lists, their lengths and the slot table live in a fixed
+ * 16 MiB device array of the library, one per device, found once per device
+ * with hipGetSymbolAddress; no side stream is used (the corrector runs after
+ * the last predictor iteration on `stream`).  Limits: at most 2,097,120 cells
+ * (AFE_E_ARG beyond), the current device must be the one cd was built on
+ * (AFE_E_ARG), cd must not be attached to a batch (AFE_E_ARG).  Every call
+ * on a device shares that device's array: calls that overlap on one device
+ * (two host threads, or two streams without ordering) race.  Other errors
+ * and the report as for ader_step. */
+afe_status ader_step_noalloc(afe_cell_data *cd, double *u, double dt, afe_step_report *rep, void *stream);
+
 /* Copy the last predictor solution (the space-time nodal values q of
  * eq:ader4) to device memory q [ndof][(N+1)*5]: DOF-major, then time node,
  * then conserved variable. */

@@ -31,7 +31,7 @@ EXPORTED = [
     "afe_subgrid_host", "afe_profile_enable", "afe_profile_read", "afe_estimate_bytes",
     "afe_batch_create", "afe_batch_free", "afe_batch_attach", "afe_batch_detach", "afe_batch_step",
     "afe_batch_set_shape", "afe_batch_get_shape", "afe_batch_tune", "afe_batch_profile_enable",
-    "afe_batch_profile_read", "afe_l2_points", "afe_l2_error",
+    "afe_batch_profile_read", "ader_step_noalloc", "afe_l2_points", "afe_l2_error",
 ]
 BATCH_SLOTS = 64
 
@@ -114,6 +114,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "ader_predict": ([vp, vp, dbl, vp], i32),
         "ader_correct": ([vp, vp, dbl, vp], i32),
         "ader_step": ([vp, vp, dbl, ctypes.POINTER(_Report), vp], i32),
+        "ader_step_noalloc": ([vp, vp, dbl, ctypes.POINTER(_Report), vp], i32),
         "afe_predictor_state": ([vp, vp, vp], i32),
         "afe_cell_diagnostics": ([vp, vp, vp, vp], i32),
         "afe_free": ([vp], None),
@@ -319,6 +320,12 @@ class CellData:
         _check(_lib.ader_step(self._h, _dev(u), float(dt), ctypes.byref(rep) if report else None, _stream(stream)))
         if not report:
             return None
+        return StepReport(rep.iters_min, rep.iters_max, rep.iters_mean, rep.n_troubled, rep.status_cell)
+
+    def step_noalloc(self, u, dt: float, stream=None) -> StepReport:
+        """ader_step_noalloc: the same step without any device allocation."""
+        rep = _Report()
+        _check(_lib.ader_step_noalloc(self._h, _dev(u), float(dt), ctypes.byref(rep), _stream(stream)))
         return StepReport(rep.iters_min, rep.iters_max, rep.iters_mean, rep.n_troubled, rep.status_cell)
 
     def l2_points(self, stream=None):

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -82,6 +83,8 @@ struct Engine {
     bool allow_correct = false;
     // batch_step_on reached the per-slot reports of this call
     bool reported = false;
+    // early passes on a side stream allowed (off for the allocation-free step)
+    bool side_ok = true;
     bool forked2 = false;
     hipGraphExec_t g_pre = nullptr, g_post = nullptr, g_chunk[2] = {nullptr, nullptr};
     // profiling of the first group's M^{-1} launches
@@ -145,6 +148,8 @@ struct afe_cell_data {
     double *d_scalar = nullptr;  // device scratch scalar (largest CFL term)
     int32_t *h_status = nullptr; // pinned host copy of the status words
     double *h_scalar = nullptr;  // pinned host scalars [2]: largest CFL term, dt
+    int32_t *h_counts = nullptr; // pinned host list lengths of the allocation-free step
+    int device = 0;              // device the object's memory lives on
     Engine solo;                 // this object as the only slot
     afe_batch *batch = nullptr;  // batch it is attached to, if any
 
@@ -173,6 +178,7 @@ struct afe_cell_data {
         for (void *p : allocs) (void)hipFree(p);
         if (h_status) (void)hipHostFree(h_status);
         if (h_scalar) (void)hipHostFree(h_scalar);
+        if (h_counts) (void)hipHostFree(h_counts);
     }
 };
 
@@ -482,7 +488,8 @@ afe_status iterate(Engine &E, hipStream_t s) {
         HIP_TRY(hipStreamSynchronize(s));
         total = 0;
         for (size_t gi = 0; gi < E.groups.size(); ++gi) total += upper[gi] = E.h_counts[gi];
-        if (!E.forked && total > 0 && total * kEarlyFraction <= all_cells) AFE_TRY(launch_early_post(E, it, upper, s));
+        if (E.side_ok && !E.forked && total > 0 && total * kEarlyFraction <= all_cells)
+            AFE_TRY(launch_early_post(E, it, upper, s));
         if (E.allow_correct && E.forked && !E.forked2 && total > 0 && total * kLateCorrectFraction <= all_cells)
             AFE_TRY(launch_early_correct(E, it, upper, s));
         if (E.prof_on && !graph) {
@@ -813,7 +820,9 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(w.guess_ok, 1)) != hipSuccess || (e = hipMemsetAsync(w.guess_ok, 0, sizeof(int32_t), s)) != hipSuccess ||
         (e = cd->alloc(w.status, kStatusWords)) != hipSuccess || (e = cd->alloc(cd->d_scalar, 1)) != hipSuccess ||
         (e = hipHostMalloc(&cd->h_status, kStatusWords * sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipHostMalloc(&cd->h_scalar, 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess) {
+        (e = hipHostMalloc(&cd->h_scalar, 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipHostMalloc(&cd->h_counts, sizeof(int32_t), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipGetDevice(&cd->device)) != hipSuccess) {
         std::string m = hipGetErrorString(e);
         delete cd;
         return fail(e == hipErrorOutOfMemory ? AFE_E_HBM_BUDGET : AFE_E_HIP, "allocation: " + m);
@@ -1018,6 +1027,137 @@ afe_status ader_step(afe_cell_data *cd, double *u, double dt, afe_step_report *r
     const afe_status st = status_of(h[0]);
     if (st != AFE_OK) return fail(st, status_text(st));
     return AFE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ------------------------------------------------ allocation-free step
+//
+// The step's only device memory beyond the object's own buffers (built once
+// by build_afe_cell_data) is the engine's slot table, its two list lengths
+// and its two predictor lists; ader_step allocates them lazily, and again
+// whenever it is handed another state.  The allocation-free step keeps them
+// in this file-scope array instead, one copy per device (each device that
+// runs the library holds it until the process ends), laid out as
+//   [0, kScratchTable)                          slot table (one DevSlot)
+//   [kScratchTable, kScratchTable + 256)        list lengths (2 int32)
+//   [kScratchTable + 256, kScratchBytes)        lists (2 x n_cells int32)
+// Every call on a device shares that device's array and overwrites it; calls
+// that overlap on one device race.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+constexpr size_t kScratchTable = (sizeof(afe::DevSlot) + 255) & ~size_t(255);
+constexpr size_t kScratchLists = kScratchTable + 256;
+constexpr int64_t kScratchMaxCells = int64_t((kScratchBytes - kScratchLists) / (2 * sizeof(int32_t)));
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (the array's name is a host-side stand-in, not a device address).
+afe_status scratch_address(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(AFE_E_ARG, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(AFE_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = static_cast<unsigned char *>(g_scratch_dev[dev]);
+    return AFE_OK;
+}
+
+// An engine over one object whose table, lists and list lengths point into
+// the scratch array; it owns nothing (its destructor frees nothing).
+struct ScratchEngine {
+    Engine E;
+    ~ScratchEngine() {
+        E.d_tab = nullptr;
+        E.h_counts = nullptr;
+        for (auto &gr : E.groups) gr.lists = gr.counts = nullptr;
+        E.groups.clear();
+    }
+};
+
+afe_status step_noalloc(afe_cell_data *cd, double *u, double dt, afe_step_report *rep, hipStream_t s) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != cd->device) return fail(AFE_E_ARG, "the current device is not the object's device");
+    if (int64_t(cd->host.n_cells) > kScratchMaxCells)
+        return fail(AFE_E_ARG, "mesh has " + std::to_string(cd->host.n_cells) + " cells; the allocation-free step takes at most " +
+                                   std::to_string(kScratchMaxCells));
+    unsigned char *base = nullptr;
+    AFE_TRY(scratch_address(dev, &base));
+    if (cd->solo.u[0] != u) {  // another state: the predictor starts from u^n
+        cd->solo.u[0] = u;
+        cd->solo.dirty = true;
+        HIP_TRY(afe::launch_set_count(cd->w.guess_ok, 0, s));
+    }
+    ScratchEngine se;
+    Engine &E = se.E;
+    E.side_ok = false;
+    E.cds[0] = cd;
+    E.u[0] = u;
+    E.tab[0].g = cd->g;
+    E.tab[0].w = cd->w;
+    E.tab[0].w.u = u;
+    Group gr;
+    gr.N = cd->g.N;
+    gr.mixed = cd->g.mixed;
+    gr.visc = cd->g.kappa != 0.0 ? 2 : (cd->g.mu != 0.0 || cd->g.av) ? 1 : 0;
+    gr.slots.push_back(0);
+    gr.base.push_back(0);
+    gr.cells = cd->host.n_cells;
+    gr.max_cell_dofs = cd->host.max_cell_dofs;
+    gr.max_cell_subtets = cd->host.max_cell_subtets;
+    gr.resident = afe::resident_shape(gr.N, gr.mixed, gr.visc);
+    gr.counts = reinterpret_cast<int32_t *>(base + kScratchTable);
+    gr.lists = reinterpret_cast<int32_t *>(base + kScratchLists);
+    E.groups.push_back(gr);
+    E.d_tab = reinterpret_cast<afe::DevSlot *>(base);
+    E.h_counts = cd->h_counts;
+    E.dirty = false;
+    E.shape = cd->solo.shape;
+    E.shape.graph = 0;
+    // the table lives in host memory of this call until the final synchronisation
+    HIP_TRY(hipMemcpyAsync(E.d_tab, E.tab.data(), sizeof(afe::DevSlot), hipMemcpyHostToDevice, s));
+    apply_shape(E);
+    HIP_TRY(afe::launch_set_dt(cd->w, dt, s));
+    AFE_TRY(launch_pre(E, false, s));  // list lengths and lists are written here
+    AFE_TRY(iterate(E, s));
+    HIP_TRY(afe::launch_pred_post(cd->g, E.tab[0].w, 2, s));
+    HIP_TRY(afe::launch_correct(cd->g, cd->w, u, 1, s));
+    HIP_TRY(afe::launch_step_stats(cd->g, cd->w, s));
+    HIP_TRY(hipMemcpyAsync(cd->h_status, cd->w.status, kStatusWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const int32_t *h = cd->h_status;
+    if (rep) {
+        unsigned long long sum = 0;
+        std::memcpy(&sum, h + 6, sizeof(sum));
+        rep->iters_min = h[4];
+        rep->iters_max = h[5];
+        rep->iters_mean = cd->host.n_cells ? double(sum) / double(cd->host.n_cells) : 0.0;
+        rep->n_troubled = h[3];
+        rep->status_cell = h[0] ? h[1] : -1;
+    }
+    const afe_status st = status_of(h[0]);
+    if (st != AFE_OK) return fail(st, status_text(st));
+    return AFE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+afe_status ader_step_noalloc(afe_cell_data *cd, double *u, double dt, afe_step_report *rep, void *stream) {
+    if (!cd || !u || !(dt > 0.0)) return fail(AFE_E_ARG, "invalid argument");
+    if (cd->batch) return fail(AFE_E_ARG, "object is attached to a batch");
+    return step_noalloc(cd, u, dt, rep, static_cast<hipStream_t>(stream));
 }
 
 afe_status afe_l2_points(afe_cell_data *cd, const double *dof_xyz, double *xq, int32_t *nq, void *stream) {
