@@ -438,6 +438,142 @@ def large_mesh_leg(log, steps: int = 3, history_cells: int = 2048) -> dict:
     return out
 
 
+STABILITY = {
+    # configured meshes: (seeds per side, jitter, seed, N, steps per CFL number)
+    "wave6_p2": (6, 0.2, 0, 2, 2000),
+    "wave16_p3": (16, 0.25, 1, 3, 400),
+}
+STABILITY_CFL = (0.004, 0.008, 0.016, 0.03, 0.06, 0.12, 0.25, 0.5)
+
+
+def stability_scan(log, keys=tuple(STABILITY), cfls=STABILITY_CFL, eps: float = 1e-3) -> dict:
+    """CFL certification by the power iteration of the linearised step.  On
+    the density wave family (velocity (1,1,1), p = 1, rho = 1 + delta) every
+    flux is affine in rho and the uniform state is a fixed point of the step,
+    so the step maps delta linearly.  From a seeded random delta, each step
+    advances 1 + eps delta / ||delta|| and takes the new delta; the product of
+    the norms' ratios is the amplification, the geometric mean over the last
+    quarter of the steps the asymptotic growth per step.  A CFL number is
+    certified when every step succeeds, the late growth is at most 1 + 1e-4
+    and the amplification stays below 100 (transients of the sub-grid noise
+    aside, no mode grows)."""
+    import numpy as np
+    import torch
+
+    from afe_inputs.mesh import jittered_lattice_seeds, periodic_voronoi
+    from paper_2605_00619_amd import afe
+
+    out = {}
+    for key in keys:
+        n, jit, seed, N, steps = STABILITY[key]
+        mesh = periodic_voronoi(jittered_lattice_seeds(n, jit, seed))
+        cd = afe.CellData(mesh, N, afe.Params(max_iter=400))
+        gen = torch.Generator(device="cuda").manual_seed(seed)
+        base = torch.ones(5, cd.ndof, dtype=torch.float64, device="cuda")
+        base[4] = 1.0 / 0.4 + 1.5
+        rows = []
+        for cfl in cfls:
+            dt = cd.cfl_dt(base, cfl)
+            d = torch.rand(cd.ndof, dtype=torch.float64, device="cuda", generator=gen) * 2.0 - 1.0
+            norms, status, iters = [], "AFE_OK", 0
+            t0 = time.time()
+            for _ in range(steps):
+                rho = 1.0 + eps * d / torch.linalg.vector_norm(d)
+                u = torch.stack([rho, rho, rho, rho, 1.0 / 0.4 + 1.5 * rho]).contiguous()
+                try:
+                    rep = cd.step(u, dt)
+                except afe.AfeError as e:
+                    status = e.name
+                    break
+                iters = max(iters, rep.iters_max)
+                d = (u[0] - 1.0) / eps
+                norms.append(float(torch.linalg.vector_norm(d)))
+            g = np.array(norms)
+            amp = float(np.exp(np.cumsum(np.log(g))).max()) if len(g) else float("nan")
+            q = max(1, len(g) // 4)
+            late = float(np.exp(np.mean(np.log(g[-q:])))) if len(g) else float("nan")
+            ok = status == "AFE_OK" and late <= 1.0 + 1e-4 and amp < 100.0
+            rows.append({"cfl": cfl, "dt": dt, "steps": len(g), "status": status, "amplification_max": amp,
+                         "late_growth_per_step": late, "predictor_iters_max": iters, "stable": ok})
+            log(f"[stability {key}] CFL {cfl}: {rows[-1]} ({time.time() - t0:.1f}s)")
+        certified = max([r["cfl"] for r in rows if r["stable"] and all(x["stable"] for x in rows if x["cfl"] <= r["cfl"])],
+                        default=None)
+        out[key] = {"cells": cd.n_cells, "N": N, "ndof": cd.ndof, "scan": rows, "certified_cfl": certified}
+        cd.close()
+        torch.cuda.empty_cache()
+    return out
+
+
+def configured_runs(log, cfl: float = 0.004, long_steps: int = 1000) -> dict:
+    """Workloads run to their configured ends (density wave, FP64):
+    - the 6^3-seed mesh (+-0.2 h, seed 0), N = 2, to t = 0.1: the L2 density
+      error of Sec. 5 against the exact translated wave (afe_l2_error);
+    - the 16^3-seed mesh (+-0.25 h, seed 1), N = 3, for long_steps steps: the
+      largest predictor iteration count of every step (does the stiffest
+      cells' count keep growing?) and the time per step."""
+    import numpy as np
+    import torch
+
+    from afe_inputs.fields import density_wave
+    from afe_inputs.mesh import jittered_lattice_seeds, periodic_voronoi
+    from paper_2605_00619_amd import afe
+
+    out = {}
+    mesh = periodic_voronoi(jittered_lattice_seeds(6, 0.2, 0))
+    cd = afe.CellData(mesh, 2, afe.Params(max_iter=400))
+    x = cd.dof_coords().cpu().numpy()
+    u = cd.prim_to_cons(torch.tensor(density_wave(np.mod(x.T, 1.0)).T.copy(), device="cuda"))
+    t_end, t, steps, imax = 0.1, 0.0, 0, []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while t < t_end:
+        dt = min(cd.cfl_dt(u, cfl), t_end - t)
+        rep = cd.step(u, dt)
+        t += dt
+        steps += 1
+        imax.append(rep.iters_max)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    xq = cd.l2_points().cpu().numpy()
+    err = cd.l2_error(u, 0, torch.tensor(density_wave(np.mod(xq, 1.0), t=t_end)[:, 0], device="cuda"))
+    out["wave6_p2_to_t0.1"] = {"cells": cd.n_cells, "ndof": cd.ndof, "steps": steps, "cfl": cfl, "wall_s": wall,
+                               "dof_updates_per_s": 5 * cd.ndof * steps / wall, "l2_density_error": err,
+                               "iters_max_first_last": [imax[0], imax[-1]], "iters_max_max": int(max(imax))}
+    log(f"[configured] {out['wave6_p2_to_t0.1']}")
+    cd.close()
+    mesh = periodic_voronoi(jittered_lattice_seeds(16, 0.25, 1))
+    cd = afe.CellData(mesh, 3, afe.Params(max_iter=400))
+    x = cd.dof_coords().cpu().numpy()
+    u = cd.prim_to_cons(torch.tensor(density_wave(np.mod(x.T, 1.0)).T.copy(), device="cuda"))
+    b = afe.Batch()
+    b.attach(cd, u, cfl)
+    imax, imean, t = [], [], 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(long_steps):
+        r = b.step()[0]
+        t += r.dt
+        imax.append(r.iters_max)
+        imean.append(r.iters_mean)
+        if (k + 1) % 100 == 0:
+            log(f"[configured] wave16_p3 step {k + 1}: t {t:.5f}, iterations max of the last 100 steps "
+                f"{max(imax[-100:])}, mean {np.mean(imean[-100:]):.3f}")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    xq = cd.l2_points().cpu().numpy()
+    err = cd.l2_error(u, 0, torch.tensor(density_wave(np.mod(xq, 1.0), t=t)[:, 0], device="cuda"))
+    blocks = [int(max(imax[i:i + 100])) for i in range(0, long_steps, 100)]
+    out["wave16_p3_long"] = {"steps": long_steps, "t_end": t, "ms_per_step": 1e3 * wall / long_steps,
+                             "dof_updates_per_s": 5 * cd.ndof * long_steps / wall,
+                             "iters_max_per_100_steps": blocks, "iters_mean": float(np.mean(imean)),
+                             "l2_density_error": err}
+    log(f"[configured] {out['wave16_p3_long']}")
+    b.close()
+    cd.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,11 +596,25 @@ def main() -> int:
                     help="skip the mixed-precision and mesh-variant legs")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--configured-runs", action="store_true",
+                    help="only the density wave 6^3 N=2 to t=0.1 and 1000 steps of 16^3 N=3 (one JSON line)")
+    ap.add_argument("--stability", action="store_true",
+                    help="only the CFL certification scan of the configured meshes (one JSON line)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic record from two counter runs and exit")
     args = ap.parse_args()
     if args.summarize_counters:
         return summarize_counters(*args.summarize_counters)
+    if args.configured_runs:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(configured_runs(log)), flush=True)
+        return 0
+    if args.stability:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps(stability_scan(log)), flush=True)
+        return 0
     if args.serve_only:
         import torch
         torch.cuda.set_device(0)
