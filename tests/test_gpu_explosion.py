@@ -17,7 +17,7 @@ can have arrived, r < 1 - R - 2.5 t; the L2 density error (Sec. 5's norm,
 afe_l2_error) is taken over that ball, in FP64 and in mixed precision.
 Bars: the FP64 error is below 2% of the density jump times the ball's volume
 root (the interface spans a few cells at this resolution), and the mixed
-precision error is within twice FP64's (the benchmark spec)."""
+precision error is within twice FP64's."""
 import math
 
 import numpy as np

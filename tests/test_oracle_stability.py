@@ -1,4 +1,4 @@
-"""Stability probe of the step (the survey's test layer 6) on the oracle.
+"""Stability probe of the step (power iteration of the linearised step) on the oracle.
 
 On the density wave family (velocity (1,1,1), p = 1, rho = 1 + delta) every
 flux is affine in rho and the uniform state is a fixed point of the step
