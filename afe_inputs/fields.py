@@ -60,3 +60,43 @@ def taylor_green_3d(x: np.ndarray, mach: float = 0.1, gamma: float = 1.4) -> np.
 def uniform_state(x: np.ndarray, prim=(1.0, 0.3, -0.2, 0.1, 1.0)) -> np.ndarray:
     """A constant state (free-stream)."""
     return np.tile(np.asarray(prim, dtype=np.float64), (len(x), 1))
+
+
+def isentropic_vortex(x: np.ndarray, t: float = 0.0, strength: float = 5.0, centre=(5.0, 5.0),
+                      vel=(0.0, 0.0, 0.0), gamma: float = 1.4) -> np.ndarray:
+    """Two-dimensional isentropic vortex (Sec. 5.1-5.2): with r the distance
+    from the centre (x_c + u_0 t, y_c + v_0 t) in the (x, y) plane and the
+    temperature perturbation dT = -(gamma - 1) eps^2 / (8 gamma pi^2)
+    exp(1 - r^2),
+        rho = (1 + dT)^(1 / (gamma - 1)),  p = (1 + dT)^(gamma / (gamma - 1)),
+        (u, v) = vel + eps / (2 pi) exp((1 - r^2) / 2) (-(y - y_c), x - x_c),
+    w = vel_z.  With vel = 0 it is steady; with a constant background
+    velocity it translates with it.  Exact for the Euler equations."""
+    x = np.asarray(x, dtype=np.float64)
+    vel = np.asarray(vel, dtype=np.float64)
+    dx = x[:, 0] - (centre[0] + vel[0] * t)
+    dy = x[:, 1] - (centre[1] + vel[1] * t)
+    r2 = dx * dx + dy * dy
+    dT = -(gamma - 1.0) * strength ** 2 / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    a = strength / (2.0 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    out = np.empty((len(x), 5))
+    out[:, 0] = (1.0 + dT) ** (1.0 / (gamma - 1.0))
+    out[:, 1] = vel[0] - a * dy
+    out[:, 2] = vel[1] + a * dx
+    out[:, 3] = vel[2]
+    out[:, 4] = (1.0 + dT) ** (gamma / (gamma - 1.0))
+    return out
+
+
+def affine_density(x: np.ndarray, t: float = 0.0, grad=(0.05, -0.03, 0.02), rho0: float = 1.0,
+                   vel=(0.4, 0.3, -0.2), p0: float = 1.0) -> np.ndarray:
+    """rho = rho0 + grad . (x - vel t), constant velocity and pressure: a
+    translating density affine in space and time, an exact solution of the
+    Euler equations (every flux is affine in rho at constant v and p)."""
+    x = np.asarray(x, dtype=np.float64)
+    vel = np.asarray(vel, dtype=np.float64)
+    out = np.empty((len(x), 5))
+    out[:, 0] = rho0 + (x - vel * t) @ np.asarray(grad, dtype=np.float64)
+    out[:, 1:4] = vel
+    out[:, 4] = p0
+    return out

@@ -1,4 +1,5 @@
-"""Seeded periodic Voronoi meshes of a box [0, L)^3.
+"""Seeded Voronoi meshes of a box: periodic ([0, L)^3) or bounded
+([0, Lx] x [0, Ly] x [0, Lz], cells clipped to the box).
 
 This module only generates input geometry: it knows nothing of the AFE
 sub-grid, the basis or the scheme.  Both the CPU oracle and the HIP library
@@ -11,11 +12,15 @@ Mesh arrays (all numpy, C order):
                                    from the owner cell (right-hand rule)
     face_vshift  int8    [sum, 3]  image shift of each corner: its position in
                                    the owner's frame is xyz[v] + shift * L
-    face_cell    int32   [nf, 2]   (owner, neighbour)
+    face_cell    int32   [nf, 2]   (owner, neighbour); neighbour -1 marks a face
+                                   on the boundary of a bounded mesh
     nbr_shift    int8    [nf, 3]   neighbour seed in the owner's frame is
                                    seeds[nbr] + nbr_shift * L
     seeds        float64 [nc, 3]
-    box          float64           L
+    box          float64           L (bounded meshes: the largest side; no
+                                   shifts are used there)
+    bounded      bool              True for a bounded mesh (all shifts zero)
+    lengths      float64 [3]       box sides (bounded meshes)
 """
 from __future__ import annotations
 
@@ -188,6 +193,144 @@ def periodic_voronoi(seeds: np.ndarray, box: float = 1.0, margin: float | None =
         seeds=seeds.copy(),
         box=float(box),
         n_cells=n,
+        bounded=False,
+        lengths=np.full(3, float(box)),
+    )
+    _check_closed(mesh)
+    return mesh
+
+
+def jittered_box_seeds(counts, lengths, jitter: float, seed: int) -> np.ndarray:
+    """nx ny nz seeds in [0, Lx] x [0, Ly] x [0, Lz]: lattice points
+    ((i, j, k) + 1/2) h_d, h_d = L_d / n_d, each moved by a uniform offset in
+    [-jitter h_d, +jitter h_d] per direction (jitter < 1/2 keeps every seed
+    inside).  Lattice in C order over (i, j, k); the offsets are one
+    (nx ny nz, 3) uniform draw of default_rng(seed), scaled per direction."""
+    counts = np.asarray(counts, dtype=np.int64)
+    lengths = np.asarray(lengths, dtype=np.float64)
+    if not 0.0 <= jitter < 0.5:
+        raise ValueError("jitter must lie in [0, 1/2)")
+    h = lengths / counts
+    idx = np.stack(np.meshgrid(*(np.arange(c) for c in counts), indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(seed)
+    jit = rng.uniform(-jitter, jitter, size=(len(idx), 3)) * h
+    return (idx + 0.5) * h + jit
+
+
+def box_voronoi(seeds: np.ndarray, lengths, merge_tol: float | None = None) -> dict:
+    """Voronoi tessellation of `seeds` clipped to the box [0, Lx] x [0, Ly] x
+    [0, Lz].
+
+    The diagram is taken of the seeds together with their mirror images
+    across the six box planes: for a point inside the box a mirror image is
+    never nearer than the seed it mirrors, and outside the box beyond a plane
+    the seed's own mirror is nearer than the seed, so each seed's cell is its
+    Voronoi cell clipped to the box, and the face between a seed and its own
+    mirror lies in the plane.  Faces to a mirror are boundary faces
+    (neighbour -1).  Vertices closer than merge_tol times the mean seed
+    spacing are merged as in periodic_voronoi (default 1e-3 of the mean
+    spacing); every cell must stay inside the box and the cell volumes must
+    add up to the box volume (checked by the callers' tests)."""
+    seeds = np.asarray(seeds, dtype=np.float64)
+    lengths = np.asarray(lengths, dtype=np.float64).reshape(3)
+    n = len(seeds)
+    if n < 2:
+        raise ValueError("a bounded Voronoi mesh needs at least 2 seeds")
+    if np.any(seeds <= 0.0) or np.any(seeds >= lengths):
+        raise ValueError("seeds must lie inside the box")
+    spacing = float(np.prod(lengths) / n) ** (1.0 / 3.0)
+    if merge_tol is None:
+        merge_tol = 1e-3
+    margin = 4.0 * spacing
+    pts, mir = [seeds], [np.arange(n)]
+    for d in range(3):
+        for side in (0.0, lengths[d]):
+            near = np.abs(seeds[:, d] - side) < margin
+            p = seeds[near].copy()
+            p[:, d] = 2.0 * side - p[:, d]
+            pts.append(p)
+            mir.append(np.nonzero(near)[0])
+    pts = np.concatenate(pts)
+    orig = np.concatenate(mir)  # seed each point is (an image of)
+    vor = Voronoi(pts)
+    rp = vor.ridge_points
+    own_mask = (rp[:, 0] < n) | (rp[:, 1] < n)
+    used = sorted({v for r, m in zip(vor.ridge_vertices, own_mask) if m for v in r})
+    if -1 in used:
+        raise RuntimeError("unbounded Voronoi region touches a cell")
+    used = np.array(used)
+    vpos = vor.vertices[used]
+    tol = 1e-9 * float(lengths.max())
+    if np.any(vpos < -tol) or np.any(vpos > lengths + tol):
+        raise RuntimeError("a cell reaches outside the box")
+    vpos = np.clip(vpos, 0.0, lengths)
+    tree = cKDTree(vpos)
+    pairs = tree.query_pairs(merge_tol * spacing, output_type="ndarray")
+    parent = np.arange(len(used))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for a, b in pairs:
+        ra, rb = find(a), find(b)
+        if ra != rb:
+            parent[max(ra, rb)] = min(ra, rb)
+    roots = np.array([find(i) for i in range(len(used))])
+    uroots, canon = np.unique(roots, return_inverse=True)
+    xyz = vpos[uroots]
+    if np.linalg.norm(vpos - xyz[canon], axis=1).max() > 0.05 * spacing:
+        raise RuntimeError("merge tolerance too large for this seed spacing")
+    vmap = -np.ones(len(vor.vertices), dtype=np.int64)
+    vmap[used] = canon
+
+    faces = []  # (owner, neighbour or -1, ridge)
+    for r, (a, b) in enumerate(rp):
+        if a >= n and b >= n:
+            continue
+        if a < n and b < n:
+            faces.append((min(a, b), max(a, b), r))
+        else:
+            own, oth = (a, b) if a < n else (b, a)
+            faces.append((int(own), -1, r))
+    faces.sort()
+    face_ptr = [0]
+    face_vtx, face_cell = [], []
+    for own, nb, r in faces:
+        a, b = rp[r]
+        oth = b if a == own else a
+        nrm = pts[oth] - pts[own]
+        nrm /= np.linalg.norm(nrm)
+        vids = np.array(vor.ridge_vertices[r])
+        _, first = np.unique(vmap[vids], return_index=True)
+        vids = vids[np.sort(first)]
+        if len(vids) < 3:
+            continue
+        vp = vor.vertices[vids]
+        ctr = vp.mean(axis=0)
+        e1 = vp[0] - ctr
+        e1 -= nrm * np.dot(e1, nrm)
+        e1 /= np.linalg.norm(e1)
+        e2 = np.cross(nrm, e1)
+        order = np.argsort(np.arctan2((vp - ctr) @ e2, (vp - ctr) @ e1))
+        face_vtx.extend(vmap[vids[order]].tolist())
+        face_ptr.append(len(face_vtx))
+        face_cell.append((own, nb))
+    nfc = len(face_cell)
+    mesh = dict(
+        xyz=np.ascontiguousarray(xyz, dtype=np.float64),
+        face_ptr=np.array(face_ptr, dtype=np.int32),
+        face_vtx=np.array(face_vtx, dtype=np.int32),
+        face_vshift=np.zeros((len(face_vtx), 3), dtype=np.int8),
+        face_cell=np.array(face_cell, dtype=np.int32).reshape(-1, 2),
+        nbr_shift=np.zeros((nfc, 3), dtype=np.int8),
+        seeds=seeds.copy(),
+        box=float(lengths.max()),
+        n_cells=n,
+        bounded=True,
+        lengths=lengths.copy(),
     )
     _check_closed(mesh)
     return mesh
@@ -204,6 +347,8 @@ def _check_closed(mesh: dict) -> None:
     for f in range(len(fc)):
         for side in (0, 1):
             c = int(fc[f, side])
+            if c < 0:
+                continue
             corners = list(range(fp[f], fp[f + 1]))
             if side == 1:
                 corners = corners[::-1]
@@ -229,6 +374,8 @@ def mesh_stats(mesh: dict) -> dict:
     for f in range(len(fc)):
         k = fp[f + 1] - fp[f]
         for c in fc[f]:
+            if c < 0:
+                continue
             nf[c] += 1
             ne2[c] += k
     return dict(faces_per_cell=nf, subtets_per_cell=ne2)

@@ -51,6 +51,15 @@ R15 (heat conduction, Sec. 2): kappa is a constant of the simulation, not
    R = (gamma - 1) c_v (c_v a parameter, 2.5 as in the paper's viscous test);
    the second viscous eigenvalue gamma mu / (Pr rho) with Pr = mu gamma c_v /
    kappa is kappa / (c_v rho).
+R21 (Dirichlet boundaries, Sec. 5.1-5.2 "Dirichlet boundary conditions on all
+   sides" with the exact solution): on a bounded mesh a boundary sub-triangle
+   takes as its "+" side the exact solution at its face nodes' positions at
+   the predictor's time nodes t^n + tau_a dt, so qbar+ = dt sum_a w_a q_e(a)
+   and Fbar+ = dt sum_a w_a F(q_e(a)); the Rusanov flux of R5 is then taken
+   as at an interior triangle, with the "+" wave speeds from qbar+ / dt.  The
+   detector (R6) counts no velocity jump and no outside sound speed across a
+   boundary triangle.  Boundaries are taken for the Euler equations only
+   (mu = kappa = 0, no artificial viscosity).
 """
 from __future__ import annotations
 
@@ -106,6 +115,8 @@ def dof_counts(mesh: dict, N: int) -> np.ndarray:
     for f, cells in enumerate(mesh["face_cell"]):
         k = int(fp[f + 1] - fp[f])
         for c in cells:
+            if c < 0:  # boundary face: one cell only
+                continue
             F[c] += 1
             E[c] += k
             verts[c].update(int(v) for v in mesh["face_vtx"][fp[f]:fp[f + 1]])
@@ -124,10 +135,17 @@ class Oracle:
     neighbours when artificial viscosity is on, are built as needed).
     """
 
-    def __init__(self, mesh: dict, N: int, params: Params = Params(), cells=None):
+    def __init__(self, mesh: dict, N: int, params: Params = Params(), cells=None, boundary=None):
         self.mesh = mesh
         self.N = N
         self.p = params
+        # exact solution for the Dirichlet data of a bounded mesh (R21):
+        # boundary(x [n, 3], t) -> primitive (rho, u, v, w, p) [n, 5]
+        self.bounded = bool(mesh.get("bounded", False))
+        self.boundary = boundary
+        self.t = 0.0
+        if self.bounded and (params.mu != 0.0 or params.kappa != 0.0 or params.av):
+            raise ValueError("boundaries are taken for the Euler equations only (R21)")
         self.ref = ref_element(N)
         self.tb = time_basis(N)
         n = mesh["n_cells"]
@@ -141,7 +159,8 @@ class Oracle:
         if params.av and cells is not None:
             for c in self.targets:
                 for f, side in cf[c]:
-                    paired.add(int(mesh["face_cell"][f][1 - side]))
+                    if mesh["face_cell"][f][1 - side] >= 0:
+                        paired.add(int(mesh["face_cell"][f][1 - side]))
         self.paired = sorted(paired)
         self.grids = build_cells(mesh, N, self.paired)
         for c, g in self.grids.items():
@@ -183,7 +202,7 @@ class Oracle:
         u = np.zeros((5, self.ndof))
         L = self.mesh["box"]
         for c, g in self.grids.items():
-            w = field_fn(np.mod(g.dof_x, L))
+            w = field_fn(g.dof_x if self.bounded else np.mod(g.dof_x, L))
             u[:, self.dof_ptr[c]:self.dof_ptr[c + 1]] = prim_to_cons(w, self.p.gamma).T
         return u
 
@@ -199,6 +218,9 @@ class Oracle:
         cmin = math.inf
         for k in range(len(g.conn)):
             qi = uc[g.face_dof[k]]
+            if g.nbr[k] < 0:  # boundary triangle: no jump, inside sound speed only (R21)
+                cmin = min(cmin, float(sound_speed(qi, gam).min()))
+                continue
             qo = self.cell_state(u, int(g.nbr[k]))[g.nbr_face_dof[k]]
             vi = qi[:, 1:4] / qi[:, :1]
             vo = qo[:, 1:4] / qo[:, :1]
@@ -328,10 +350,14 @@ class Oracle:
         gam = self.p.gamma
         N = self.N
         nb = int(g.nbr[k])
-        kn = int(g.nbr_tri[k])
-        perm = g.nbr_perm[k]
         qi, Fi = ti[c]["tq"][k], ti[c]["tF"][k]
-        qo, Fo = ti[nb]["tq"][kn][perm], ti[nb]["tF"][kn][perm]
+        if nb < 0:
+            qo, Fo = self.boundary_traces(c, k, dt)
+            nb = c  # viscosity and length scale of the inside (mu = 0 here, R21)
+        else:
+            kn = int(g.nbr_tri[k])
+            perm = g.nbr_perm[k]
+            qo, Fo = ti[nb]["tq"][kn][perm], ti[nb]["tF"][kn][perm]
         n = g.tri_normal[k]
         wi, wo = qi / dt, qo / dt
         vi = wi[:, 1:4] / wi[:, :1]
@@ -343,6 +369,18 @@ class Oracle:
         eps = (2 * N + 1) / ((g.h + self.grids[nb].h) * math.sqrt(math.pi / 2.0))
         s = lam + 2.0 * eps * lamv
         return 0.5 * np.einsum("jxv,x->jv", Fo + Fi, n) - 0.5 * s * (qo - qi)
+
+    def boundary_traces(self, c: int, k: int, dt: float):
+        """qbar+ [nf, 5] and Fbar+ [nf, 3, 5] of the exact solution at the face
+        nodes of cell c's boundary triangle k over the step (R21)."""
+        if self.boundary is None:
+            raise ValueError("a bounded mesh needs the exact solution for its boundary data")
+        g = self.grids[c]
+        x = g.dof_x[g.face_dof[k]]
+        qa = np.stack([prim_to_cons(self.boundary(x, self.t + tau * dt), self.p.gamma) for tau in self.tb.tau])
+        qbar = dt * np.einsum("a,ajv->jv", self.tb.w, qa)
+        Fbar = dt * np.einsum("a,ajxv->jxv", self.tb.w, flux(qa, self.p.gamma))
+        return qbar, Fbar
 
     def face_term(self, c: int, ti: dict, mus: dict, dt: float) -> np.ndarray:
         """sum_t P_t^T 2 A_t Z^ G_t (R5)."""
@@ -358,13 +396,15 @@ class Oracle:
         """Target cells and their face neighbours."""
         ring = set(self.targets)
         for c in self.targets:
-            ring.update(int(x) for x in self.grids[c].nbr)
+            ring.update(int(x) for x in self.grids[c].nbr if x >= 0)
         return sorted(ring)
 
-    def step(self, u: np.ndarray, dt: float, depth=None, tol=None, max_iter=None, keep=False):
-        """One ADER step: detector, predictor, corrector, positivity check.
-        Returns (u_new, report); only target cells of u_new are updated.
-        keep=True also stores the predictor results in report.pred / report.ti."""
+    def step(self, u: np.ndarray, dt: float, depth=None, tol=None, max_iter=None, keep=False, t: float = 0.0):
+        """One ADER step from time t: detector, predictor, corrector, positivity
+        check.  Returns (u_new, report); only target cells of u_new are updated.
+        keep=True also stores the predictor results in report.pred / report.ti.
+        t matters only for the boundary data of a bounded mesh (R21)."""
+        self.t = float(t)
         rep = StepReport()
         ring = self.ring()
         mus = {}
@@ -412,6 +452,6 @@ class Oracle:
             for k in range(len(g.conn)):
                 x = g.X[k, 0] + pts @ g.J[k].T
                 uh = phi @ uc[g.conn[k]]
-                ue = exact_fn(np.mod(x, L))
+                ue = exact_fn(x if self.bounded else np.mod(x, L))
                 tot += g.detJ[k] * float(wts @ (uh - ue) ** 2)
         return math.sqrt(tot)

@@ -41,7 +41,8 @@ class CellGrid:
     J, detJ, G      [K, 3, 3] Jacobian, |det J| [K], G = J^{-1} (row d = grad xi_d)
     tri_area        [K] area of each sub-tet's boundary triangle
     tri_normal      [K, 3] unit normal of it, outward from this cell
-    nbr             [K] neighbour cell across that triangle
+    nbr             [K] neighbour cell across that triangle (-1: boundary of a
+                    bounded mesh; then nbr_tri = -1, nbr_face_dof = -1)
     nbr_tri         [K] index of the same triangle among the neighbour's sub-tets
     nbr_perm        [K, nf] face node j of this triangle is node nbr_perm[j] of the neighbour's
     face_dof        [K, nf] cell DOF of each face node
@@ -79,7 +80,8 @@ def faces_of_cells(mesh: dict) -> list[list[tuple[int, int]]]:
     lst = [[] for _ in range(n)]
     for f, (o, nb) in enumerate(mesh["face_cell"]):
         lst[int(o)].append((f, 0))
-        lst[int(nb)].append((f, 1))
+        if nb >= 0:  # a bounded mesh's boundary faces have no neighbour
+            lst[int(nb)].append((f, 1))
     return lst
 
 
@@ -172,7 +174,9 @@ def build_cells(mesh: dict, N: int, cells=None) -> dict[int, CellGrid]:
     need = set(cells)
     for c in cells:
         for f, side in cf[c]:
-            need.add(int(mesh["face_cell"][f][1 - side]))
+            other = int(mesh["face_cell"][f][1 - side])
+            if other >= 0:
+                need.add(other)
     grids = {c: build_cell(mesh, c, N, cf) for c in sorted(need)}
     R = ref_element(N)
     fn = R.face_nodes_a
@@ -211,6 +215,11 @@ def build_cells(mesh: dict, N: int, cells=None) -> dict[int, CellGrid]:
             g.tri_area[k] = area
             g.tri_normal[k] = nvec
             g.nbr[k] = other
+            if other < 0:  # boundary triangle of a bounded mesh: no partner
+                g.nbr_tri[k] = -1
+                g.nbr_perm[k] = np.arange(len(fn))
+                g.nbr_face_dof[k] = -1
+                continue
             h = grids[other]
             # neighbour's sub-tet on the same triangle: edge (b, a) on face f
             kn = h.tri_index[(f, b_id, a_id)]

@@ -6,7 +6,9 @@ CPU), points the pin test at the changed module and expects the pin to fail:
 - the symmetric part of the velocity gradient replaced by 2 mu grad v,
 - the viscous penalty 2 eps |lambda^v| dropped from the Rusanov flux (eq. 3.33),
 - the face mass matrix Z^ lumped to its row sums (Sec. 4.4),
-- the time weights w_a dropped from the predictor's stiffness term (eq:ader4).
+- the time weights w_a dropped from the predictor's stiffness term (eq:ader4),
+- the boundary data taken at the start of the step instead of at the time
+  nodes, or with the "+" side's own face nodes reversed (R21).
 """
 import importlib.util
 import os
@@ -20,6 +22,7 @@ from afe_inputs.mesh import jittered_lattice_seeds, periodic_voronoi
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
+import test_oracle_boundary as boundary_pins  # noqa: E402
 import test_oracle_navier_stokes as pins  # noqa: E402
 import test_oracle_scheme as scheme_pins  # noqa: E402
 
@@ -88,3 +91,18 @@ def test_dropped_time_weights_are_caught(monkeypatch, mesh3):
     monkeypatch.setattr(scheme_pins, "Oracle", mod.Oracle)
     with pytest.raises(AssertionError):
         scheme_pins.test_predictor_reproduces_translated_polynomial(mesh3, 2)
+
+
+BOUNDARY = [
+    ("boundary data at t^n", "self.boundary(x, self.t + tau * dt)", "self.boundary(x, self.t + 0.0 * tau * dt)"),
+    ("boundary face nodes reversed", "x = g.dof_x[g.face_dof[k]]", "x = g.dof_x[g.face_dof[k]][::-1]"),
+]
+
+
+@pytest.mark.parametrize("name,old,new", BOUNDARY, ids=[b[0] for b in BOUNDARY])
+def test_boundary_mutation_is_caught(monkeypatch, name, old, new):
+    boundary_pins.test_affine_solution_reproduced_with_boundary_data(2)
+    mod = _mutated("scheme", old, new)
+    monkeypatch.setattr(boundary_pins, "Oracle", mod.Oracle)
+    with pytest.raises(AssertionError):
+        boundary_pins.test_affine_solution_reproduced_with_boundary_data(2)
