@@ -280,9 +280,14 @@ def box_voronoi(seeds: np.ndarray, lengths, merge_tol: float | None = None) -> d
             parent[max(ra, rb)] = min(ra, rb)
     roots = np.array([find(i) for i in range(len(used))])
     uroots, canon = np.unique(roots, return_inverse=True)
-    xyz = vpos[uroots]
+    xyz = vpos[uroots].copy()
     if np.linalg.norm(vpos - xyz[canon], axis=1).max() > 0.05 * spacing:
         raise RuntimeError("merge tolerance too large for this seed spacing")
+    # a merged vertex stays on every box plane one of its members lies on
+    for d in range(3):
+        for side in (0.0, lengths[d]):
+            on = np.abs(vpos[:, d] - side) <= tol
+            xyz[np.unique(canon[on]), d] = side
     vmap = -np.ones(len(vor.vertices), dtype=np.int64)
     vmap[used] = canon
 

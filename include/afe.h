@@ -45,12 +45,15 @@ typedef enum {
     AFE_E_NONFINITE = -8          /* NaN or Inf in the state after the update       */
 } afe_status;
 
-/* Polyhedral mesh of a periodic cube [0, box)^3 (host arrays, copied).
- * Each vertex is stored once; a face is a polygon listed once, oriented outward
- * from its owner by the right-hand rule; a corner's position in the owner's
- * frame is xyz[v] + face_vshift[corner] * box, and the neighbour's seed in the
- * owner's frame is shifted by nbr_shift * box, so the neighbour sees the
- * corner at xyz[v] + (face_vshift - nbr_shift) * box. */
+/* Polyhedral mesh of a periodic cube [0, box)^3 or of a bounded domain (host
+ * arrays, copied).  Each vertex is stored once; a face is a polygon listed
+ * once, oriented outward from its owner by the right-hand rule; a corner's
+ * position in the owner's frame is xyz[v] + face_vshift[corner] * box, and the
+ * neighbour's seed in the owner's frame is shifted by nbr_shift * box, so the
+ * neighbour sees the corner at xyz[v] + (face_vshift - nbr_shift) * box.
+ * A face whose neighbour is -1 lies on the boundary of a bounded mesh (its
+ * shifts are 0); the solution there is given by Dirichlet data, see
+ * afe_set_boundary_states. */
 typedef struct {
     int32_t n_vertices;
     const double *xyz;          /* [n_vertices][3]                              */
@@ -58,7 +61,7 @@ typedef struct {
     const int32_t *face_ptr;    /* [n_faces + 1] CSR offsets into face_vtx      */
     const int32_t *face_vtx;    /* [face_ptr[n_faces]] corner vertex ids         */
     const int8_t *face_vshift;  /* [face_ptr[n_faces]][3] corner image shifts    */
-    const int32_t *face_cell;   /* [n_faces][2] owner, neighbour                 */
+    const int32_t *face_cell;   /* [n_faces][2] owner, neighbour (-1: boundary)  */
     const int8_t *nbr_shift;    /* [n_faces][3] neighbour image shift            */
     int32_t n_cells;
     double box;                 /* edge of the periodic cube                    */
@@ -146,10 +149,33 @@ afe_status afe_dof_coords(const afe_cell_data *cd, double *xyz, void *stream);
  *   subtet_ptr [n_cells + 1] int64, conn [n_subtets][np] int32 cell-local DOF of
  *   each sub-tet node (np = (N+1)(N+2)(N+3)/6, App. A node order),
  *   nbr_subtet [n_subtets] int32 global index of the neighbour's sub-tet on the
- *   same boundary triangle, nbr_perm [n_subtets][nf] int32 matching face node.
+ *   same boundary triangle (-1 - b on boundary triangle b of a bounded mesh,
+ *   b counting those triangles in ascending sub-tet order), nbr_perm
+ *   [n_subtets][nf] int32 matching face node (j itself on a boundary triangle).
  * Any output pointer may be NULL. */
 afe_status afe_connectivity(const afe_cell_data *cd, int64_t *subtet_ptr, int32_t *conn,
                             int32_t *nbr_subtet, int32_t *nbr_perm);
+
+/* Dirichlet data of a bounded mesh (Sec. 5.1-5.2: the exact solution imposed
+ * on all sides).  A boundary triangle's outside state in the Rusanov flux of
+ * Sec. 4.4 is the given solution at its face nodes at the predictor's time
+ * nodes t^n + tau_a dt: qbar = dt sum_a w_a q_a and Fbar = dt sum_a w_a F(q_a)
+ * (Euler flux); the detector of Sec. 4.5 counts no velocity jump across it.
+ * afe_boundary_nodes writes *count = (boundary triangles) * nf, the boundary
+ * face nodes (triangle b's face node j is node b * nf + j, triangles in
+ * ascending sub-tet order), and, when not NULL, their coordinates xyz host
+ * [count][3] and the N+1 time nodes tau host [N+1] in (0, 1).
+ * afe_set_boundary_states registers prim, device [count][N+1][5]: the
+ * primitive state (rho, u, v, w, p) at each boundary node and time node of the
+ * next step; caller-owned, read by every following ader_step, ader_correct
+ * and ader_step_noalloc, so the caller refills it (for the new t^n and dt)
+ * before each step; NULL unregisters.  A step of a bounded object without
+ * registered states fails with AFE_E_ARG.  Bounded objects take the Euler
+ * equations only (build_afe_cell_data fails with AFE_E_ARG for mu, kappa or
+ * av) and are stepped alone with the caller's dt (afe_batch_attach fails with
+ * AFE_E_ARG).  Errors: AFE_E_ARG. */
+afe_status afe_boundary_nodes(const afe_cell_data *cd, int64_t *count, double *xyz, double *tau);
+afe_status afe_set_boundary_states(afe_cell_data *cd, const double *prim);
 
 /* Host-only construction of the same sub-grid (no device memory, no GPU):
  * afe_subgrid_sizes returns sizes[0] = number of sub-tets, sizes[1] = number

@@ -32,6 +32,7 @@ EXPORTED = [
     "afe_batch_create", "afe_batch_free", "afe_batch_attach", "afe_batch_detach", "afe_batch_step",
     "afe_batch_set_shape", "afe_batch_get_shape", "afe_batch_tune", "afe_batch_profile_enable",
     "afe_batch_profile_read", "ader_step_noalloc", "afe_l2_points", "afe_l2_error",
+    "afe_boundary_nodes", "afe_set_boundary_states",
 ]
 BATCH_SLOTS = 64
 
@@ -120,6 +121,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afe_free": ([vp], None),
         "afe_l2_points": ([vp, vp, vp, ctypes.POINTER(i32), vp], i32),
         "afe_l2_error": ([vp, vp, i32, vp, ctypes.POINTER(dbl), vp], i32),
+        "afe_boundary_nodes": ([vp, ctypes.POINTER(ctypes.c_int64), vp, vp], i32),
+        "afe_set_boundary_states": ([vp, vp], i32),
         "afe_subgrid_sizes": ([ctypes.POINTER(_Mesh), i32, vp], i32),
         "afe_subgrid_host": ([ctypes.POINTER(_Mesh), i32, vp, vp, vp, vp, vp, vp, vp], i32),
         "afe_last_error": ([], ctypes.c_char_p),
@@ -345,6 +348,31 @@ class CellData:
         out = ctypes.c_double()
         _check(_lib.afe_l2_error(self._h, _dev(u), int(var), _dev(ref), ctypes.byref(out), _stream(stream)))
         return float(out.value)
+
+    # ------------------------------------------------- Dirichlet boundaries
+    def boundary_nodes(self):
+        """(xyz [count, 3], tau [N + 1]) as numpy: the boundary face nodes of a
+        bounded mesh (count = 0 for a periodic one) and the predictor's time
+        nodes in (0, 1); the Dirichlet data of a step from t with time step
+        dt is the solution at (xyz[i], t + tau[a] dt)."""
+        count = ctypes.c_int64()
+        _check(_lib.afe_boundary_nodes(self._h, ctypes.byref(count), None, None))
+        xyz = np.zeros((count.value, 3))
+        tau = np.zeros(self.N + 1)
+        _check(_lib.afe_boundary_nodes(self._h, ctypes.byref(count), xyz.ctypes.data, tau.ctypes.data))
+        return xyz, tau
+
+    def set_boundary_states(self, prim) -> None:
+        """Register the Dirichlet data, primitive (rho, u, v, w, p) device
+        [count, N + 1, 5] (None unregisters).  The tensor is read by every
+        following step: keep it alive and refill it before each step."""
+        if prim is not None:
+            count = ctypes.c_int64()
+            _check(_lib.afe_boundary_nodes(self._h, ctypes.byref(count), None, None))
+            if tuple(prim.shape) != (count.value, self.N + 1, 5):
+                raise ValueError(f"boundary states must have shape ({count.value}, {self.N + 1}, 5)")
+        self._bstate = prim
+        _check(_lib.afe_set_boundary_states(self._h, None if prim is None else _dev(prim)))
 
     def predictor_state(self, stream=None):
         import torch

@@ -231,6 +231,13 @@ afe_status check_params(const afe_params *p) {
     return AFE_OK;
 }
 
+// A bounded mesh's corrector reads the caller's boundary states.
+afe_status check_boundary(const afe_cell_data *cd) {
+    if (cd->host.n_btri > 0 && !cd->g.bstate)
+        return fail(AFE_E_ARG, "bounded mesh: no boundary states registered (afe_set_boundary_states)");
+    return AFE_OK;
+}
+
 // ----------------------------------------------------------------- engine
 
 afe_status ensure_stream(Engine &E) {
@@ -658,6 +665,10 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     cd->params = *params;
     const afe::HostGrid &h = cd->host;
     const int depth = params->accel_depth;
+    if (h.n_btri > 0 && (params->mu != 0.0 || params->kappa != 0.0 || params->av)) {
+        delete cd;
+        return fail(AFE_E_ARG, "a bounded mesh takes the Euler equations only (mu = kappa = 0, no artificial viscosity)");
+    }
     if (h.n_cells >= afe::kMaxCellsPerSlot) {
         delete cd;
         return fail(AFE_E_ARG, "too many cells");
@@ -691,6 +702,8 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     g.av = params->av;
     g.mixed = params->precision == AFE_MIXED ? 1 : 0;
     g.guess = params->predictor_guess;
+    g.bstate = nullptr;
+    g.n_btri = h.n_btri;
     std::vector<int64_t> minv_ptr(h.n_cells + 1, 0), minv32_ptr(h.n_cells + 1, 0);
     for (int c = 0; c < h.n_cells; ++c) {
         int64_t n = h.dof_ptr[c + 1] - h.dof_ptr[c];
@@ -854,6 +867,7 @@ afe_status afe_estimate_bytes(const afe_mesh *mesh, int32_t N, const afe_params 
         const int k = mesh->face_ptr[f + 1] - mesh->face_ptr[f];
         for (int side = 0; side < 2; ++side) {
             const int c = mesh->face_cell[2 * f + side];
+            if (side == 1 && c == -1) continue;  // boundary face of a bounded mesh
             if (c < 0 || c >= nc) return fail(AFE_E_BAD_MESH, "face cell out of range");
             F[c] += 1;
             E[c] += k;
@@ -917,6 +931,25 @@ afe_status afe_connectivity(const afe_cell_data *cd, int64_t *subtet_ptr, int32_
     return AFE_OK;
 }
 
+afe_status afe_boundary_nodes(const afe_cell_data *cd, int64_t *count, double *xyz, double *tau) {
+    if (!cd || !count) return fail(AFE_E_ARG, "null argument");
+    const afe::HostGrid &h = cd->host;
+    *count = h.n_btri * h.nf;
+    if (xyz && !h.bnode_x.empty()) std::memcpy(xyz, h.bnode_x.data(), h.bnode_x.size() * sizeof(double));
+    if (tau) {
+        const afe::RefData &R = afe::ref_data(h.N);
+        for (int a = 0; a <= h.N; ++a) tau[a] = R.tau[a];
+    }
+    return AFE_OK;
+}
+
+afe_status afe_set_boundary_states(afe_cell_data *cd, const double *prim) {
+    if (!cd) return fail(AFE_E_ARG, "null argument");
+    if (prim && cd->host.n_btri == 0) return fail(AFE_E_ARG, "the mesh has no boundary faces");
+    cd->g.bstate = prim;
+    return AFE_OK;
+}
+
 afe_status afe_subgrid_sizes(const afe_mesh *mesh, int32_t N, int64_t *sizes) {
     if (!mesh || !sizes) return fail(AFE_E_ARG, "null argument");
     afe::HostGrid h;
@@ -972,6 +1005,7 @@ namespace {
 // the same step, so the corrector may start early for cells that allow it.
 afe_status predict_impl(afe_cell_data *cd, const double *u, double dt, void *stream, bool full) {
     if (!cd || !u || !(dt > 0.0)) return fail(AFE_E_ARG, "invalid argument");
+    if (full) AFE_TRY(check_boundary(cd));
     hipStream_t s = static_cast<hipStream_t>(stream);
     Engine &E = cd->solo;
     if (E.u[0] != u) {
@@ -1001,6 +1035,7 @@ afe_status ader_predict(afe_cell_data *cd, const double *u, double dt, void *str
 
 afe_status ader_correct(afe_cell_data *cd, double *u, double dt, void *stream) {
     if (!cd || !u || !(dt > 0.0)) return fail(AFE_E_ARG, "invalid argument");
+    AFE_TRY(check_boundary(cd));
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(afe::launch_set_dt(cd->w, dt, s));
     HIP_TRY(afe::launch_correct(cd->g, cd->w, u, 1, s));
@@ -1085,6 +1120,7 @@ struct ScratchEngine {
 };
 
 afe_status step_noalloc(afe_cell_data *cd, double *u, double dt, afe_step_report *rep, hipStream_t s) {
+    AFE_TRY(check_boundary(cd));
     int dev = -1;
     HIP_TRY(hipGetDevice(&dev));
     if (dev != cd->device) return fail(AFE_E_ARG, "the current device is not the object's device");
@@ -1231,6 +1267,8 @@ void afe_batch_free(afe_batch *b) {
 afe_status afe_batch_attach(afe_batch *b, afe_cell_data *cd, double *u, double cfl, int32_t *slot) {
     if (!b || !cd || !u || !(cfl > 0.0)) return fail(AFE_E_ARG, "invalid argument");
     if (cd->batch) return fail(AFE_E_ARG, "object already attached to a batch");
+    if (cd->host.n_btri > 0)
+        return fail(AFE_E_ARG, "a bounded mesh is stepped alone: its caller fills the boundary states for each time step");
     Engine &E = b->eng;
     int sl = 0;
     while (sl < afe::kMaxSlots && E.cds[sl]) ++sl;

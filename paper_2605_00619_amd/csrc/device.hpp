@@ -58,8 +58,13 @@ struct DevGrid {
     const int32_t *sub_cell;  // [nsub]
     const double *geo;        // [nsub][10]
     const double *tri;        // [nsub][4]
-    const int32_t *nbr_sub;   // [nsub]
+    const int32_t *nbr_sub;   // [nsub]; -1 - b on boundary triangle b of a bounded mesh
     const int32_t *perm;      // [nsub][nf]
+    // Dirichlet data of a bounded mesh: primitive states (rho, u, v, w, p) at
+    // boundary face node b * nf + j and time node a, [n_btri * nf][nt][5]
+    // (caller-owned; null when none are registered)
+    const double *bstate;
+    int64_t n_btri;
     const double *h, *vol;    // [n_cells]
     const double *mrow;       // [ndof]
     const int32_t *dof_cell;  // [ndof]

@@ -368,13 +368,16 @@ __global__ void __launch_bounds__(256) k_detect(DevGrid g, DevWork w, const doub
         const int j = int(e % nf);
         const int64_t li = d0 + g.conn[k * np + g.ref->fn[j]];
         const int64_t kn = g.nbr_sub[k];
+        double qi[5], qo[5];
+        for (int v = 0; v < 5; ++v) qi[v] = u[v * nd + li];
+        if (kn < 0) {
+            // boundary triangle of a bounded mesh: no jump, inside sound speed only
+            cmin = fmin(cmin, sqrt(gam * pressure5(qi, gam) / qi[0]));
+            continue;
+        }
         const int jn = g.perm[k * nf + j];
         const int64_t lo = g.dof_ptr[g.sub_cell[kn]] + g.conn[kn * np + g.ref->fn[jn]];
-        double qi[5], qo[5];
-        for (int v = 0; v < 5; ++v) {
-            qi[v] = u[v * nd + li];
-            qo[v] = u[v * nd + lo];
-        }
+        for (int v = 0; v < 5; ++v) qo[v] = u[v * nd + lo];
         const double *T = g.tri + k * 4;
         const double jn_ = (qo[1] / qo[0] - qi[1] / qi[0]) * T[1] + (qo[2] / qo[0] - qi[2] / qi[0]) * T[2] +
                            (qo[3] / qo[0] - qi[3] / qi[0]) * T[3];
@@ -575,7 +578,7 @@ __global__ void __launch_bounds__(256) k_mark_late2(const DevSlot *__restrict__ 
         const DevWork &w = tab[slot].w;
         if (threadIdx.x == 0) w.late2[c] = 1;
         for (int64_t k = g.sub_ptr[c] + threadIdx.x; k < g.sub_ptr[c + 1]; k += blockDim.x)
-            w.late2[g.sub_cell[g.nbr_sub[k]]] = 1;
+            if (g.nbr_sub[k] >= 0) w.late2[g.sub_cell[g.nbr_sub[k]]] = 1;
     }
 }
 
@@ -1537,6 +1540,31 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
 
 // ------------------------------------------------------------- corrector
 
+// Outside trace of a boundary face node of a bounded mesh from the Dirichlet
+// data: the exact state q_a at the predictor's time nodes (primitive, from
+// g.bstate), qbar = dt sum_a w_a q_a and Fbar_x = dt sum_a w_a F_x(q_a) with
+// the Euler flux, laid out as a trace entry: qbar (5), Fbar (3 x 5).
+template <int N>
+__device__ inline void boundary_trace(const DevGrid &g, int64_t node, double dt, double tb[20]) {
+    constexpr int nt = N + 1;
+    for (int e = 0; e < 20; ++e) tb[e] = 0.0;
+    const double *s = g.bstate + node * nt * 5;
+    const double gam = g.gamma;
+    for (int a = 0; a < nt; ++a) {
+        const double r = s[a * 5], vx = s[a * 5 + 1], vy = s[a * 5 + 2], vz = s[a * 5 + 3], p = s[a * 5 + 4];
+        const double q[5] = {r, r * vx, r * vy, r * vz, p / (gam - 1.0) + 0.5 * r * (vx * vx + vy * vy + vz * vz)};
+        double F[3][5];
+        const double gq[3][5] = {};
+        ns_flux<false>(q, gq, gam, 0.0, 0.0, g.cv, F);
+        const double wa = g.ref->w[a];
+        for (int v = 0; v < 5; ++v) {
+            tb[v] += wa * q[v];
+            for (int x = 0; x < 3; ++x) tb[5 + 5 * x + v] += wa * F[x][v];
+        }
+    }
+    for (int e = 0; e < 20; ++e) tb[e] *= dt;
+}
+
 // Rusanov flux with viscous penalty (eq. 3.33) at the face nodes of every
 // boundary sub-triangle, contracted with the face mass: fc[k][j'] =
 // 2 A_k sum_j Z^[j'][j] G_j.  One value of the dissipation coefficient per
@@ -1556,15 +1584,22 @@ __global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w, int which) {
     double eps = 0.0;
     if (valid) {
         const int64_t kn = g.nbr_sub[k];
-        const int jn = g.perm[k * nf + j];
         const double *ti = w.trace + (k * nf + j) * 20;
-        const double *to = w.trace + (kn * nf + jn) * 20;
+        const double *to;
+        double tb[20];
+        if (kn >= 0) {
+            to = w.trace + (kn * nf + g.perm[k * nf + j]) * 20;
+        } else {
+            boundary_trace<N>(g, (-1 - kn) * nf + j, dt, tb);
+            to = tb;
+        }
         const double *T = g.tri + k * 4;
         a2 = T[0];
         nrm[0] = T[1];
         nrm[1] = T[2];
         nrm[2] = T[3];
-        const int ci = g.sub_cell[k], co = g.sub_cell[kn];
+        // outside viscosity and length scale: the cell's own at a boundary (mu = 0 there)
+        const int ci = g.sub_cell[k], co = kn >= 0 ? g.sub_cell[kn] : ci;
         double qi[5], qo[5];
         const double idt = 1.0 / dt;
         for (int v = 0; v < 5; ++v) {

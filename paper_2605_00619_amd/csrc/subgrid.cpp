@@ -113,13 +113,14 @@ afe_status build_host_grid(const afe_mesh &mesh, int N, HostGrid &g, std::string
     // faces of each cell, ascending face id
     std::vector<std::vector<std::pair<int, int>>> cell_faces(nc);
     for (int f = 0; f < mesh.n_faces; ++f) {
+        // neighbour -1: a face on the boundary of a bounded mesh
         int o = mesh.face_cell[2 * f], n = mesh.face_cell[2 * f + 1];
-        if (o < 0 || o >= nc || n < 0 || n >= nc || o == n || mesh.face_ptr[f + 1] - mesh.face_ptr[f] < 3) {
+        if (o < 0 || o >= nc || n < -1 || n >= nc || o == n || mesh.face_ptr[f + 1] - mesh.face_ptr[f] < 3) {
             err = "face " + std::to_string(f) + " has invalid cells or fewer than 3 corners";
             return AFE_E_BAD_MESH;
         }
         cell_faces[o].push_back({f, 0});
-        cell_faces[n].push_back({f, 1});
+        if (n >= 0) cell_faces[n].push_back({f, 1});
     }
     std::vector<double> mhat_colsum(np, 0.0);
     for (int m = 0; m < np; ++m)
@@ -344,11 +345,26 @@ afe_status build_host_grid(const afe_mesh &mesh, int N, HostGrid &g, std::string
     auto tkey = [](int f, int a, int b) { return (int64_t(f) << 42) ^ (int64_t(a) << 21) ^ int64_t(b); };
     for (int c = 0; c < nc; ++c)
         for (size_t k = 0; k < cb[c].face.size(); ++k) tri_of[c][tkey(cb[c].face[k], cb[c].ea[k], cb[c].eb[k])] = int(k);
+    g.n_btri = 0;
+    g.bnode_x.clear();
     for (int c = 0; c < nc; ++c) {
         const CellBuild &B = cb[c];
         for (size_t k = 0; k < B.face.size(); ++k) {
             int f = B.face[k];
             int o = mesh.face_cell[2 * f], nb = mesh.face_cell[2 * f + 1];
+            int64_t gk = g.sub_ptr[c] + int64_t(k);
+            if (nb < 0) {
+                // boundary triangle b (ascending sub-tet order): nbr_sub = -1 - b,
+                // face node j is its own partner, coordinates of its face nodes kept
+                const int64_t b = g.n_btri++;
+                g.nbr_sub[gk] = int32_t(-1 - b);
+                for (int j = 0; j < nf; ++j) {
+                    g.perm[size_t(gk) * nf + j] = j;
+                    const int64_t l = g.dof_ptr[c] + B.conn[k * np + R.face_nodes[j]];
+                    for (int d = 0; d < 3; ++d) g.bnode_x.push_back(g.dof_x[size_t(d) * g.ndof + l]);
+                }
+                continue;
+            }
             int other = (c == o) ? nb : o;
             auto it = tri_of[other].find(tkey(f, B.eb[k], B.ea[k]));
             if (it == tri_of[other].end()) {
@@ -356,7 +372,7 @@ afe_status build_host_grid(const afe_mesh &mesh, int N, HostGrid &g, std::string
                 return AFE_E_BAD_MESH;
             }
             int kn = it->second;
-            int64_t gk = g.sub_ptr[c] + int64_t(k), gkn = g.sub_ptr[other] + kn;
+            int64_t gkn = g.sub_ptr[other] + kn;
             g.nbr_sub[gk] = int32_t(gkn);
             const CellBuild &Bn = cb[other];
             for (int j = 0; j < nf; ++j) {

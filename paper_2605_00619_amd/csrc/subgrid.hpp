@@ -1,5 +1,5 @@
 // Host construction of the sub-tetrahedral grid, the agglomerated cell DOFs
-// and the boundary-triangle pairing of a periodic polyhedral mesh.
+// and the boundary-triangle pairing of a periodic or bounded polyhedral mesh.
 #pragma once
 #include <cstdint>
 #include <string>
@@ -21,7 +21,10 @@ struct HostGrid {
     std::vector<int32_t> sub_cell;  // [nsub]
     std::vector<double> geo;        // [nsub][10]: G = J^{-1} row-major (9), |det J|
     std::vector<double> tri;        // [nsub][4]: 2 * area, unit normal (outward)
-    std::vector<int32_t> nbr_sub;   // [nsub] neighbour's sub-tet on the same triangle
+    std::vector<int32_t> nbr_sub;   // [nsub] neighbour's sub-tet on the same triangle; -1 - b on
+                                    // boundary triangle b of a bounded mesh
+    int64_t n_btri = 0;             // boundary triangles (bounded meshes)
+    std::vector<double> bnode_x;    // [n_btri][nf][3] coordinates of their face nodes
     std::vector<int32_t> perm;      // [nsub][nf] matching face node in the neighbour
     std::vector<double> h, vol;     // [n_cells] diameter, volume
     std::vector<double> mrow;       // [ndof] int_P phi_l (column sums of M_i)

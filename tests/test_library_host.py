@@ -42,6 +42,31 @@ def test_host_subgrid_matches_oracle(mesh_4, N):
     assert (np.abs(a2 - h["tri"][:, 0]) / a2).max() < 1e-14
 
 
+@pytest.mark.parametrize("N", [1, 3])
+def test_host_subgrid_matches_oracle_on_a_bounded_mesh(N):
+    """Bounded mesh: the sub-grid equals the oracle's, boundary triangles are
+    numbered in ascending sub-tet order with nbr_subtet = -1 - b and nbr_perm
+    the identity."""
+    from afe_inputs.mesh import box_voronoi, jittered_box_seeds
+    from oracle.scheme import dof_counts
+    from oracle.subgrid import build_cells
+    L = (1.0, 1.2, 0.9)
+    mesh = box_voronoi(jittered_box_seeds((3, 3, 3), L, 0.25, 4), L)
+    h = afe.subgrid_host(mesh, N)
+    gs = build_cells(mesh, N)
+    n = mesh["n_cells"]
+    assert np.array_equal(h["dof_ptr"], np.concatenate([[0], np.cumsum(dof_counts(mesh, N))]))
+    assert np.array_equal(h["conn"], np.concatenate([gs[c].conn for c in range(n)]))
+    sp = h["subtet_ptr"]
+    onbr = np.concatenate([gs[c].nbr for c in range(n)])
+    bnd = onbr < 0
+    expect = np.concatenate([np.where(gs[c].nbr >= 0, sp[np.maximum(gs[c].nbr, 0)] + gs[c].nbr_tri, -1) for c in range(n)])
+    expect[bnd] = -1 - np.arange(bnd.sum())
+    assert np.array_equal(h["nbr_subtet"], expect)
+    assert np.array_equal(h["nbr_perm"], np.concatenate([gs[c].nbr_perm for c in range(n)]))
+    assert bnd.sum() > 0
+
+
 def test_bad_mesh_and_budget_rejected(mesh_4):
     bad = dict(mesh_4)
     fc = mesh_4["face_cell"].copy()

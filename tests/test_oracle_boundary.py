@@ -41,9 +41,12 @@ def _cell_volumes(mesh):
     return vol
 
 
-def test_box_mesh_fills_the_box():
+@pytest.mark.parametrize("merge_tol", [None, 0.05])
+def test_box_mesh_fills_the_box(merge_tol):
+    """Also with short edges collapsed: merged vertices keep the box planes
+    of their members, so the boundary stays on the box."""
     L = np.array([1.0, 1.2, 0.9])
-    m = _box_mesh(4, L)
+    m = box_voronoi(jittered_box_seeds((4, 4, 4), L, 0.25, 4), L, merge_tol=merge_tol)
     vol = _cell_volumes(m)
     assert vol.min() > 0.0
     assert abs(vol.sum() - L.prod()) < 1e-12 * L.prod()
