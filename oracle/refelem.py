@@ -42,7 +42,22 @@ def ref_nodes(N: int) -> list[tuple[Fr, Fr, Fr]]:
             (o, t3, tt3), (o, tt3, t3),
             (t3, t3, o), (t3, o, t3), (o, t3, t3), (t3, t3, t3),
         ]
-    raise ValueError("N must be 1, 2 or 3")
+    if N == 4:
+        # App. A.4 defines the 35 nodes as the lattice r, s, t in {0, 1/4, 1/2,
+        # 3/4, 1}, r + s + t <= 1, without listing them (its edge and face
+        # counts, 12 and 18, are swapped: 6 edges carry 3 nodes each, 4 faces
+        # 3 each, one node is interior).  Order taken: the vertices as above,
+        # then edge, face and interior nodes, each group lexicographic in
+        # (r, s, t).
+        lat = [(Fr(i, 4), Fr(j, 4), Fr(k, 4)) for i in range(5) for j in range(5 - i) for k in range(5 - i - j)]
+
+        def entity(p):
+            lam = (1 - sum(p),) + p
+            return sum(1 for x in lam if x != 0) - 1
+
+        rest = sorted((p for p in lat if p not in verts), key=lambda p: (entity(p), p))
+        return verts + rest
+    raise ValueError("N must be 1, 2, 3 or 4")
 
 
 def _monomials(N: int) -> list[tuple[int, int, int]]:

@@ -90,3 +90,20 @@ def test_oracle_basis_equals_printed_functions(N):
         col = order.index(at[0])
         f = np.asarray(_eval(phi, [np.asarray(v, dtype=float) for v in lam]), dtype=float)
         assert np.abs(ours[:, col] - f).max() < 1e-13
+
+
+def test_p4_nodes_are_the_appendix_lattice():
+    """App. A.4 defines the 35 quartic nodes as all (r, s, t) with r, s, t in
+    {0, 1/4, 1/2, 3/4, 1} and r + s + t <= 1, with the four vertices, one
+    interior node at (1/4, 1/4, 1/4), and the rest on edges and faces (the
+    printed counts, 12 on edges and 18 on faces, are swapped: a tetrahedron's
+    6 edges carry 3 lattice nodes each and its 4 faces 3 each)."""
+    q = [Fr(i, 4) for i in range(5)]
+    lattice = sorted((r, s, t) for r in q for s in q for t in q if r + s + t <= 1)
+    nodes = ref_nodes(4)
+    assert len(nodes) == 35 and sorted(nodes) == lattice
+    assert nodes[:4] == [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    entity = [sum(1 for x in _bary(p) if x != 0) - 1 for p in nodes]
+    assert [entity.count(d) for d in range(4)] == [4, 18, 12, 1]
+    assert nodes[entity.index(3)] == (Fr(1, 4), Fr(1, 4), Fr(1, 4))
+    assert entity == sorted(entity)  # vertices, edges, faces, interior

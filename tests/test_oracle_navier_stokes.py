@@ -122,7 +122,7 @@ def _constant_traces(o, c, q, dt):
     return dict(tq=np.broadcast_to(dt * q, (K, nf, 5)).copy(), tF=np.broadcast_to(dt * F, (K, nf, 3, 5)).copy())
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_rusanov_flux_two_states_at_rest(mesh_3, N):
     """Eq. 3.33 on a face between this cell (rho = 1) and its neighbour
     (rho = 4), both at rest with p = 1/gamma, so c = 1 and 0.5.  With the cell
@@ -151,7 +151,7 @@ def test_rusanov_flux_two_states_at_rest(mesh_3, N):
     assert np.abs(G0[:, 0] + 1.5 * dt).max() < 1e-15
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_face_mass_entrywise(N):
     """Z^[i][j] = int over the reference triangle (t = 0, area 1/2) of
     phi_{fn_i} phi_{fn_j}, by a Grundmann-Moeller rule exact to degree 2N+1;
@@ -162,7 +162,8 @@ def test_face_mass_entrywise(N):
     phi = R.eval_basis(x)
     Zq = np.einsum("q,qi,qj->ij", tw, phi, phi)
     fn = R.face_nodes_a
-    assert np.abs(R.Z_f - Zq[np.ix_(fn, fn)]).max() < 1e-15
+    # the Grundmann-Moeller rule's own rounding (mixed-sign weights) is 2e-15 at degree 9
+    assert np.abs(R.Z_f - Zq[np.ix_(fn, fn)]).max() < 1e-14
     off = np.setdiff1d(np.arange(R.np), fn)
     assert np.abs(phi[:, off]).max() < 1e-13
 

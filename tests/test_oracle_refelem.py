@@ -81,7 +81,7 @@ def test_p3_printed_functions_are_the_basis_up_to_relabelling():
     assert match[6] == 9  # printed phi_7 is the Lagrange function of x_10
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_nodal_property_partition_of_unity_and_identities(N):
     R = ref_element(N)
     V = R.eval_basis(R.nodes_f)
@@ -97,7 +97,7 @@ def test_nodal_property_partition_of_unity_and_identities(N):
             assert sum(R.D[d][m]) == 0
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_matrices_by_brute_force_quadrature(N):
     """M^, K^, D^ against Grundmann-Moeller quadrature and finite differences."""
     R = ref_element(N)
@@ -119,7 +119,7 @@ def test_matrices_by_brute_force_quadrature(N):
         assert np.abs(Dfd - R.D_f[d]).max() < 1e-6
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_stiffness_plus_transpose_is_boundary_mass(N):
     """K^_d + K^_d^T = int_T d_d(phi_m phi_l) = sum_faces n_d int_face phi_m phi_l,
     the face integrals done by quadrature on the four faces."""
@@ -142,7 +142,7 @@ def test_stiffness_plus_transpose_is_boundary_mass(N):
         assert np.abs(R.K_f[d] + R.K_f[d].T - B[d]).max() < 1e-14
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_time_basis(N):
     tb = time_basis(N)
     assert abs(tb.w.sum() - 1.0) < 1e-15
@@ -165,5 +165,5 @@ def test_time_operator_closed_form_n1():
 
 
 def test_node_lists():
-    assert [len(ref_nodes(N)) for N in (1, 2, 3)] == [4, 10, 20]
+    assert [len(ref_nodes(N)) for N in (1, 2, 3, 4)] == [4, 10, 20, 35]
     assert ref_nodes(3)[9] == (0, Fr(1, 3), 0)

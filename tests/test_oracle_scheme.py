@@ -23,7 +23,7 @@ def _affine_field(coef):
     return f
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_predictor_reproduces_translated_polynomial(mesh_3, N):
     """A field whose exact solution lies in the space-time polynomial space is
     reproduced by the local space-time Galerkin predictor (Sec. 4.3): with
