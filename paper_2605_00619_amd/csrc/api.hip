@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -735,7 +736,15 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     }
     // reference data
     const afe::RefData &R = afe::ref_data(N);
-    afe::DevRef ref{};
+    static_assert(afe::kRefNp >= afe::kMaxNp && afe::kRefNf >= afe::kMaxNf && afe::kRefNt >= afe::kMaxNt &&
+                      afe::kRefNq >= afe::kMaxNq,
+                  "device reference arrays smaller than the largest degree");
+    std::unique_ptr<afe::DevRef> ref_box(new (std::nothrow) afe::DevRef{});
+    if (!ref_box) {
+        delete cd;
+        return fail(AFE_E_ARG, "out of host memory");
+    }
+    afe::DevRef &ref = *ref_box;
     for (int i = 0; i < R.np * R.np; ++i) ref.M[i] = R.M[i];
     for (int i = 0; i < 3 * R.np * R.np; ++i) {
         ref.K[i] = R.K[i];
@@ -785,7 +794,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         ref.Ktau[i] = R.Ktau[i];
     }
     afe::DevRef *dref = nullptr;
-    if ((e = cd->alloc(dref, 1)) != hipSuccess || (e = hipMemcpyAsync(dref, &ref, sizeof(ref), hipMemcpyHostToDevice, s)) != hipSuccess) {
+    if ((e = cd->alloc(dref, 1)) != hipSuccess || (e = hipMemcpy(dref, &ref, sizeof(ref), hipMemcpyHostToDevice)) != hipSuccess) {
         std::string m = hipGetErrorString(e);
         delete cd;
         return fail(AFE_E_HIP, "reference upload: " + m);
@@ -855,7 +864,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
 
 afe_status afe_estimate_bytes(const afe_mesh *mesh, int32_t N, const afe_params *params, size_t *bytes) {
     if (!mesh || !params || !bytes) return fail(AFE_E_ARG, "null argument");
-    if (N < 1 || N > 3) return fail(AFE_E_ARG, "N must be 1, 2 or 3");
+    if (N < 1 || N > afe::kMaxN) return fail(AFE_E_ARG, "N must be 1, 2, 3 or 4");
     if (mesh->n_cells < 1 || mesh->n_faces < 1 || !mesh->face_ptr || !mesh->face_vtx || !mesh->face_cell)
         return fail(AFE_E_ARG, "empty mesh");
     // per cell: V vertices, F faces, E polygon edges; its sub-grid has

@@ -6,33 +6,40 @@
 
 namespace afe {
 
-// Reference data in device memory (one copy per object).
+// Reference data in device memory (one copy per object), sized for N <= 4;
+// entries are indexed with the object's own np, nf, nt, nq.
+constexpr int kRefNp = 35;                      // (N+1)(N+2)(N+3)/6 at N = 4
+constexpr int kRefNf = 15;                      // (N+1)(N+2)/2
+constexpr int kRefNt = 5;                       // N + 1 time nodes
+constexpr int kRefNq = 343;                     // (N+3)^3 error-norm points
+constexpr int kRefTiles = (kRefNp + 15) / 16;   // row tiles of the contraction
+constexpr int kRefSteps = (3 * kRefNp + 3) / 4; // its k-steps of 4
 struct DevRef {
-    double M[20 * 20];       // M^[m][p] = int phi_m phi_p
-    double K[3 * 20 * 20];   // K^_d[m][p] = int phi_m d_d phi_p
-    double D[3 * 20 * 20];   // D^_d[m][p] = d_d phi_p (x_m)
-    double Z[10 * 10];       // face mass on the reference triangle
-    double zsum[10];         // int_tri phi_j = sum_i Z[i][j]
-    double w[4];             // Gauss-Legendre weights on [0, 1]
-    double tau[4];           // Gauss-Legendre nodes on [0, 1]
-    double Ktau_inv[16];     // inverse of the upwind time operator
-    double Ktau[16];         // upwind time operator psi_a(1) psi_b(1) - int psi_a' psi_b
-    int fn[10];              // face node -> reference node
+    double M[kRefNp * kRefNp];       // M^[m][p] = int phi_m phi_p
+    double K[3 * kRefNp * kRefNp];   // K^_d[m][p] = int phi_m d_d phi_p
+    double D[3 * kRefNp * kRefNp];   // D^_d[m][p] = d_d phi_p (x_m)
+    double Z[kRefNf * kRefNf];       // face mass on the reference triangle
+    double zsum[kRefNf];             // int_tri phi_j = sum_i Z[i][j]
+    double w[kRefNt];                // Gauss-Legendre weights on [0, 1]
+    double tau[kRefNt];              // Gauss-Legendre nodes on [0, 1]
+    double Ktau_inv[kRefNt * kRefNt];  // inverse of the upwind time operator
+    double Ktau[kRefNt * kRefNt];      // upwind time operator psi_a(1) psi_b(1) - int psi_a' psi_b
+    int fn[kRefNf];                  // face node -> reference node
     // K^ as the A operand of the sub-tet contraction on the matrix cores:
     // tile (row tile t, k-step j) of the 16 x 4 blocks of A[m][d np + p] =
     // K^_d[m][p], zero-padded, one double per lane of v_mfma_f64_16x16x4f64
     // (A[i][k] in lane i + 16 k), at (t * steps + j) * 64 + lane with
     // steps = (3 np + 3) / 4
-    double Kfrag[2 * 15 * 64];
+    double Kfrag[kRefTiles * kRefSteps * 64];
     // The same for the mixed-precision contraction, whose inner index has a
     // fourth block: A[m][3 np + p] = M^[m][p], steps = np
-    double KMfrag[2 * 20 * 64];
+    double KMfrag[kRefTiles * kRefNp * 64];
     // volume quadrature of the error norms: points, weights (sum 1/6) and
     // basis values phi_m(xi_q) at [q * np + m]
     int nq;
-    double qxi[216 * 3];
-    double qw[216];
-    double qphi[216 * 20];
+    double qxi[kRefNq * 3];
+    double qw[kRefNq];
+    double qphi[kRefNq * kRefNp];
 };
 
 struct DevGrid {

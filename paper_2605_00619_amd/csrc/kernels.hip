@@ -1547,9 +1547,11 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
 template <int N>
 __device__ inline void boundary_trace(const DevGrid &g, int64_t node, double dt, double tb[20]) {
     constexpr int nt = N + 1;
+#pragma unroll
     for (int e = 0; e < 20; ++e) tb[e] = 0.0;
     const double *s = g.bstate + node * nt * 5;
     const double gam = g.gamma;
+#pragma unroll
     for (int a = 0; a < nt; ++a) {
         const double r = s[a * 5], vx = s[a * 5 + 1], vy = s[a * 5 + 2], vz = s[a * 5 + 3], p = s[a * 5 + 4];
         const double q[5] = {r, r * vx, r * vy, r * vz, p / (gam - 1.0) + 0.5 * r * (vx * vx + vy * vy + vz * vz)};
@@ -1557,11 +1559,14 @@ __device__ inline void boundary_trace(const DevGrid &g, int64_t node, double dt,
         const double gq[3][5] = {};
         ns_flux<false>(q, gq, gam, 0.0, 0.0, g.cv, F);
         const double wa = g.ref->w[a];
+#pragma unroll
         for (int v = 0; v < 5; ++v) {
             tb[v] += wa * q[v];
+#pragma unroll
             for (int x = 0; x < 3; ++x) tb[5 + 5 * x + v] += wa * F[x][v];
         }
     }
+#pragma unroll
     for (int e = 0; e < 20; ++e) tb[e] *= dt;
 }
 
@@ -1585,13 +1590,13 @@ __global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w, int which) {
     if (valid) {
         const int64_t kn = g.nbr_sub[k];
         const double *ti = w.trace + (k * nf + j) * 20;
-        const double *to;
-        double tb[20];
+        double to[20];  // outside trace, in registers (constant indices only)
         if (kn >= 0) {
-            to = w.trace + (kn * nf + g.perm[k * nf + j]) * 20;
+            const double *tr = w.trace + (kn * nf + g.perm[k * nf + j]) * 20;
+#pragma unroll
+            for (int e = 0; e < 20; ++e) to[e] = tr[e];
         } else {
-            boundary_trace<N>(g, (-1 - kn) * nf + j, dt, tb);
-            to = tb;
+            boundary_trace<N>(g, (-1 - kn) * nf + j, dt, to);
         }
         const double *T = g.tri + k * 4;
         a2 = T[0];
@@ -1811,6 +1816,7 @@ hipError_t dispatch(int N, F &&f) {
         case 1: return f(std::integral_constant<int, 1>{});
         case 2: return f(std::integral_constant<int, 2>{});
         case 3: return f(std::integral_constant<int, 3>{});
+        case 4: return f(std::integral_constant<int, 4>{});
         default: return hipErrorInvalidValue;
     }
 }

@@ -58,7 +58,7 @@ struct Rat {
     }
 };
 
-constexpr int kDeg = 8;  // exponents up to 2N + 1 < 8
+constexpr int kDeg = 9;  // total degree up to 2N = 8 (products of two basis functions at N = 4)
 struct Poly {
     Rat c[kDeg][kDeg][kDeg];
     Poly() = default;
@@ -153,7 +153,22 @@ std::vector<std::array<int, 3>> lattice(int N) {
         return {{0, 0, 0}, {3, 0, 0}, {0, 3, 0}, {0, 0, 3}, {1, 0, 0}, {2, 0, 0}, {2, 1, 0},
                 {1, 2, 0}, {0, 2, 0}, {0, 1, 0}, {0, 0, 1}, {0, 0, 2}, {1, 0, 2}, {2, 0, 1},
                 {0, 1, 2}, {0, 2, 1}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}, {1, 1, 1}};
-    throw std::invalid_argument("N must be 1, 2 or 3");
+    if (N == 4) {
+        // App. A.4 gives the quartic nodes only as the lattice; taken here:
+        // the vertices in the order above, then the edge, face and interior
+        // nodes, each group in lexicographic order of (r, s, t)
+        std::vector<std::array<int, 3>> out = {{0, 0, 0}, {4, 0, 0}, {0, 4, 0}, {0, 0, 4}};
+        for (int entity = 1; entity <= 3; ++entity)
+            for (int i = 0; i <= 4; ++i)
+                for (int j = 0; i + j <= 4; ++j)
+                    for (int k = 0; i + j + k <= 4; ++k) {
+                        const int l = 4 - i - j - k;
+                        const int nz = (i > 0) + (j > 0) + (k > 0) + (l > 0);
+                        if (nz - 1 == entity) out.push_back({i, j, k});
+                    }
+        return out;
+    }
+    throw std::invalid_argument("N must be 1, 2, 3 or 4");
 }
 
 // Legendre polynomial P_n and its derivative at x.

@@ -6,10 +6,10 @@
 
 namespace afe {
 
-constexpr int kMaxN = 3;
-constexpr int kMaxNp = 20;  // (N+1)(N+2)(N+3)/6 at N = 3
-constexpr int kMaxNf = 10;  // (N+1)(N+2)/2 at N = 3
-constexpr int kMaxNt = 4;   // N + 1 time nodes
+constexpr int kMaxN = 4;
+constexpr int kMaxNp = 35;  // (N+1)(N+2)(N+3)/6 at N = 4
+constexpr int kMaxNf = 15;  // (N+1)(N+2)/2 at N = 4
+constexpr int kMaxNt = 5;   // N + 1 time nodes
 
 struct RefData {
     int N = 0, np = 0, nf = 0, nt = 0;
@@ -36,7 +36,7 @@ struct RefData {
 
 constexpr int kMaxNq = (kMaxN + 3) * (kMaxN + 3) * (kMaxN + 3);
 
-// Builds the exact reference data for 1 <= N <= 3 (cached).
+// Builds the exact reference data for 1 <= N <= 4 (cached).
 const RefData &ref_data(int N);
 
 }  // namespace afe

@@ -91,8 +91,8 @@ struct CellBuild {
 }  // namespace
 
 afe_status build_host_grid(const afe_mesh &mesh, int N, HostGrid &g, std::string &err) {
-    if (N < 1 || N > 3) {
-        err = "N must be 1, 2 or 3";
+    if (N < 1 || N > kMaxN) {
+        err = "N must be 1, 2, 3 or 4";
         return AFE_E_ARG;
     }
     if (mesh.n_cells <= 0 || mesh.n_faces <= 0 || mesh.n_vertices <= 0 || !mesh.xyz || !mesh.face_ptr ||

@@ -46,7 +46,8 @@ def _run(afe, n, N, precision, collapsed, T=T_END, cfl=0.004):
 
 # Observed L2 orders 8^3 -> 16^3 seeds at t = 0.01; the paper's own L2 orders
 # on its meshes run up to about 0.3 below N + 1 (its Tables 2-3).
-@pytest.mark.parametrize("N,collapsed,bar", [(2, True, 2.5), (3, True, 3.5), (2, False, 2.5), (3, False, 3.5)])
+@pytest.mark.parametrize("N,collapsed,bar", [(2, True, 2.5), (3, True, 3.5), (2, False, 2.5), (3, False, 3.5),
+                                             (4, True, 4.5)])
 def test_convergence_with_mesh(N, collapsed, bar):
     """Order of the L2 density error when the seed spacing halves, against
     the design order N + 1 less 0.5."""

@@ -63,7 +63,7 @@ def _run_both(mesh, N, field, steps, cfl, params_o, params_g, dt=None, sweeps=No
     return uo, ug.cpu().numpy(), reps, cd, o, dt
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_connectivity_bit_exact(mesh_4, N):
     from oracle.subgrid import build_cells
     afe = _lib()
@@ -304,6 +304,33 @@ def test_failure_statuses(mesh_4):
     with pytest.raises(afe.AfeError) as e:
         cd.step(ug, 1e-4)
     assert e.value.name == "AFE_E_POSITIVITY"
+
+
+def test_step_parity_p4():
+    """P4 (App. A.4): one density-wave step on the 3^3-seed mesh with the
+    edges shorter than 2% of the spacing collapsed, in FP64 and in mixed
+    precision, against one oracle step (both stopping at 1e-14).  On the
+    mesh as configured the oracle's own P4 predictor needs about 480
+    iterations on the stiffest cell at a stop of 1e-12 and does not reach
+    1e-14 in 600."""
+    from oracle.scheme import Oracle, Params
+    afe = _lib()
+    mesh = periodic_voronoi(jittered_lattice_seeds(3, 0.2, 0), merge_tol=0.02 / 3)
+    o = Oracle(mesh, 4, Params(tol=TOL, max_iter=600))
+    u0 = o.initial_state(density_wave)
+    dt = o.cfl_dt(u0, 0.004)
+    uo, rep = o.step(u0, dt)
+    assert rep.converged and rep.positive
+    for prec in (afe.AFE_FP64, afe.AFE_MIXED):
+        cd = afe.CellData(mesh, 4, afe.Params(tol=TOL, max_iter=600, precision=prec))
+        assert np.array_equal(cd.dof_ptr, o.dof_ptr)
+        ug = torch.tensor(u0, device="cuda")
+        r = cd.step(ug, dt)
+        err = rel_linf_vars(ug.cpu().numpy(), uo)
+        print(f"P4 {'mixed' if prec else 'FP64'}: GPU vs oracle (mass, momentum, energy) {_fmt(err)}; "
+              f"iterations max {r.iters_max} (oracle {max(rep.iters.values())})", flush=True)
+        assert err.max() < 1e-12
+        cd.close()
 
 
 @pytest.mark.parametrize("N", [2, 3])

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert set(names) == set(afe.EXPORTED)
 
 
-@pytest.mark.parametrize("N", [1, 2, 3])
+@pytest.mark.parametrize("N", [1, 2, 3, 4])
 def test_host_subgrid_matches_oracle(mesh_4, N):
     from oracle.scheme import dof_counts
     from oracle.subgrid import build_cells
@@ -79,5 +79,5 @@ def test_bad_mesh_and_budget_rejected(mesh_4):
         afe.CellData(mesh_4, 2, afe.Params(hbm_budget=1024), stream=0)
     assert e.value.name == "AFE_E_HBM_BUDGET"
     with pytest.raises(afe.AfeError) as e:
-        afe.subgrid_host(mesh_4, 4)
+        afe.subgrid_host(mesh_4, 5)
     assert e.value.name == "AFE_E_ARG"
