@@ -70,7 +70,7 @@ def _images(seeds: np.ndarray, box: float, margin: float):
 
 
 def periodic_voronoi(seeds: np.ndarray, box: float = 1.0, margin: float | None = None,
-                     merge_tol: float | None = None) -> dict:
+                     merge_tol: float | None = None, linkage: str = "single") -> dict:
     """Periodic Voronoi tessellation of `seeds` in [0, box)^3.
 
     Every vertex is stored once (a single canonical coordinate in [0, box)),
@@ -86,6 +86,13 @@ def periodic_voronoi(seeds: np.ndarray, box: float = 1.0, margin: float | None =
     Voronoi edges shorter than that into points, which removes the
     sub-tetrahedral slivers of relative volume down to 1e-10 that such edges
     create; merge_tol = 1e-10 keeps the exact diagram.
+
+    linkage "single" merges every chain of vertices closer than the
+    tolerance into one cluster placed at its lowest-numbered member;
+    "complete" merges two clusters only while every pair of their members
+    stays within the tolerance (closest pairs first) and places a cluster at
+    the mean of its members, which keeps the cells star-shaped where long
+    chains of nearly co-spherical seeds would invert sub-tetrahedra.
     """
     seeds = np.asarray(seeds, dtype=np.float64)
     n = len(seeds)
@@ -119,16 +126,38 @@ def periodic_voronoi(seeds: np.ndarray, box: float = 1.0, margin: float | None =
             a = parent[a]
         return a
 
+    if linkage not in ("single", "complete"):
+        raise ValueError("linkage must be 'single' or 'complete'")
+    members = {i: [i] for i in range(len(used))}
+    if linkage == "complete" and len(pairs):
+        dd = wrapped[pairs[:, 0]] - wrapped[pairs[:, 1]]
+        dd -= box * np.round(dd / box)
+        pairs = pairs[np.argsort(np.linalg.norm(dd, axis=1), kind="stable")]
     for a, b in pairs:
         ra, rb = find(a), find(b)
-        if ra != rb:
-            parent[max(ra, rb)] = min(ra, rb)
+        if ra == rb:
+            continue
+        if linkage == "complete":
+            d = wrapped[members[ra]][:, None, :] - wrapped[members[rb]][None, :, :]
+            d -= box * np.round(d / box)
+            if np.linalg.norm(d, axis=2).max() > merge_tol * box:
+                continue
+        lo, hi = min(ra, rb), max(ra, rb)
+        parent[hi] = lo
+        members[lo] = members[lo] + members.pop(hi)
     roots = np.array([find(i) for i in range(len(used))])
     uroots, canon = np.unique(roots, return_inverse=True)
-    xyz = wrapped[uroots]
-    # a merged cluster must stay tiny next to the seed spacing
+    xyz = wrapped[uroots].copy()
+    if linkage == "complete":
+        for k, r in enumerate(uroots):
+            if len(members[r]) > 1:
+                d = wrapped[members[r]] - wrapped[r]
+                d -= box * np.round(d / box)
+                xyz[k] = np.mod(wrapped[r] + d.mean(axis=0), box)
+    # a merged cluster must stay small next to the seed spacing (nearly
+    # co-spherical seeds chain up to ~16 vertices of a 2% merge into one)
     spread = np.linalg.norm(wrapped - xyz[canon] - box * np.round((wrapped - xyz[canon]) / box), axis=1)
-    if spread.max() > 0.05 * box / n ** (1.0 / 3.0):
+    if spread.max() > 0.1 * box / n ** (1.0 / 3.0):
         raise RuntimeError("merge tolerance too large for this seed spacing")
     vmap = -np.ones(len(vor.vertices), dtype=np.int64)
     vmap[used] = canon
@@ -176,7 +205,7 @@ def periodic_voronoi(seeds: np.ndarray, box: float = 1.0, margin: float | None =
         # positions in the owner's frame: owner seed is an original point
         g = vmap[vids]
         sh = np.rint((vp - xyz[g]) / box).astype(np.int64)
-        if np.abs(vp - (xyz[g] + sh * box)).max() > 0.05 * box / n ** (1.0 / 3.0):
+        if np.abs(vp - (xyz[g] + sh * box)).max() > 0.1 * box / n ** (1.0 / 3.0):
             raise RuntimeError("vertex image shift mismatch")
         face_vtx.extend(g.tolist())
         face_vshift.extend(sh.tolist())
@@ -281,7 +310,7 @@ def box_voronoi(seeds: np.ndarray, lengths, merge_tol: float | None = None) -> d
     roots = np.array([find(i) for i in range(len(used))])
     uroots, canon = np.unique(roots, return_inverse=True)
     xyz = vpos[uroots].copy()
-    if np.linalg.norm(vpos - xyz[canon], axis=1).max() > 0.05 * spacing:
+    if np.linalg.norm(vpos - xyz[canon], axis=1).max() > 0.1 * spacing:
         raise RuntimeError("merge tolerance too large for this seed spacing")
     # a merged vertex stays on every box plane one of its members lies on
     for d in range(3):

@@ -143,6 +143,7 @@ class Server:
         self.sleep = sleep
         self.setup_workers = setup_workers
         self.peak_bytes = 0
+        self.peak_active = 0
         self.steps_run = 0
 
     def run(self, requests: list[Request]) -> list[Result]:
@@ -199,6 +200,7 @@ class Server:
                     elif wait > 0:
                         self.sleep(wait)
                     continue
+                self.peak_active = max(self.peak_active, len(active))
                 reps = self.be.step()
                 self.steps_run += 1
                 now = self.clock() - t0

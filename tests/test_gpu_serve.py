@@ -86,3 +86,46 @@ def test_taylor_green_request_stream():
             return np.array([sum(mrow[c] @ o.cell_state(v, c)[:, k] for c in range(o.n_cells)) for k in range(5)])
         t0, t1 = totals(u0), totals(r.state)
         assert np.abs(t1 - t0).max() < 1e-12 * np.abs(t0).max(), (r.rid, t0, t1)
+
+
+def test_served_request_matches_oracle():
+    """One Navier-Stokes Taylor-Green request (4^3 seeds with short edges
+    collapsed, N = 2, mu = 1/1600, mixed precision, stop at 1e-14, 2 steps at
+    CFL 0.004) served together with two density-wave requests: its final
+    state against the FP64 oracle stepped with its own CFL time steps, per
+    conserved quantity, within max(1e-12, 3 x the oracle's spread between
+    stops of 1e-14 and 1e-14 / 3)."""
+    import math
+    import sys
+    import os
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from _metrics import rel_linf_vars
+    from oracle.scheme import Oracle, Params
+    afe = _lib()
+    from paper_2605_00619_amd.serve import GpuBackend, Request, Server
+    box = 2 * math.pi
+    mesh = periodic_voronoi(jittered_lattice_seeds(4, 0.25, 9, box=box), box=box, merge_tol=0.02 / 4)
+    tg = lambda x: taylor_green_3d(x, mach=0.1)
+    mu = 1.0 / 1600.0
+    reqs = [Request(0, 0.0, periodic_voronoi(jittered_lattice_seeds(4, 0.25, 1)), 2, 3, 0.004, density_wave,
+                    afe.Params()),
+            Request(1, 0.0, mesh, 2, 2, 0.004, tg, afe.Params(mu=mu, tol=1e-14, max_iter=600, precision=afe.AFE_MIXED)),
+            Request(2, 0.01, periodic_voronoi(jittered_lattice_seeds(3, 0.25, 2)), 3, 2, 0.004, density_wave,
+                    afe.Params())]
+    free, _ = torch.cuda.mem_get_info()
+    res = Server(GpuBackend(), free // 2, keep_states=True).run(reqs)
+    assert all(r.status == "AFE_OK" for r in res)
+    served = res[1].state
+    finals = []
+    for tol in (1e-14, 1e-14 / 3):
+        o = Oracle(mesh, 2, Params(mu=mu, tol=tol, max_iter=600))
+        u = o.initial_state(tg)
+        for _ in range(2):
+            u, rep = o.step(u, o.cfl_dt(u, 0.004))
+            assert rep.converged and rep.positive
+        finals.append(u)
+    spread = rel_linf_vars(finals[1], finals[0])
+    err = rel_linf_vars(served, finals[0])
+    bar = np.maximum(1e-12, 3 * spread)
+    print(f"served NS request vs oracle (mass, momentum, energy): {err}, oracle spread {spread}", flush=True)
+    assert (err <= bar).all()

@@ -113,3 +113,22 @@ def test_matrices_by_brute_force_quadrature(mesh_3, N, which):
                 idx = g.conn[k]
                 So[np.ix_(idx, idx)] += g.detJ[k] * np.einsum("d,dml->ml", g.G[k][:, x], R.K_f)
             assert np.abs(S[x] - So).max() <= 1e-12 * np.abs(So).max()
+
+
+def test_complete_linkage_collapse_keeps_sub_tets_oriented():
+    """Collapsing Voronoi edges shorter than 2% of the seed spacing by single
+    linkage can chain many vertices of nearly co-spherical seeds into one
+    point and invert sub-tetrahedra (7^3 jittered seeds, seed 38: one cell);
+    complete linkage with the cluster at its mean keeps every cell's
+    sub-tets of one orientation, and the cells still tile the box."""
+    seeds = jittered_lattice_seeds(7, 0.25, 38)
+
+    def inverted(mesh):
+        gs = build_cells(mesh, 1)
+        return sum(int(not (np.all(np.linalg.det(g.J) > 0) or np.all(np.linalg.det(g.J) < 0))) for g in gs.values()), gs
+
+    bad, _ = inverted(periodic_voronoi(seeds, merge_tol=0.02 / 7))
+    assert bad > 0
+    bad, gs = inverted(periodic_voronoi(seeds, merge_tol=0.02 / 7, linkage="complete"))
+    assert bad == 0
+    assert abs(sum(polyhedron_volume(g) for g in gs.values()) - 1.0) < 1e-12
