@@ -209,7 +209,7 @@ size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub
     b += ndof * nc * sizeof(double) * (5 + 2 * size_t(std::max(hs, 1)));
     if (hs < depth)
         b += 2 * size_t(history_cells) * size_t(depth - hs) * size_t(max_cell_dofs) * nc * sizeof(double);
-    if (mixed) b += ndof * nc * sizeof(float);
+    if (mixed) b += ndof * nc * sizeof(float) + ndof * 5 * sizeof(double);  // FP32 residual, u^n DOF-major
     else b += size_t(afe::kMinvSplitK) * ndof * nc * sizeof(double);  // split M^-1 partials
     b += n_cells * size_t((max_cell_dofs + 63) / 64) * 130 * sizeof(double);
     b += size_t(nsub) * np * nc * sizeof(double);
@@ -765,6 +765,8 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
                     const int row = 16 * t + l % 16, kk = 4 * j + l / 16;
                     ref.Kfrag[(t * steps + j) * 64 + l] =
                         row < R.np && kk < inner ? R.K[((kk / R.np) * R.np + row) * R.np + kk % R.np] : 0.0;
+                    ref.Vfrag[(t * steps + j) * 64 + l] =
+                        row < R.np && kk < inner ? R.K[((kk / R.np) * R.np + kk % R.np) * R.np + row] : 0.0;
                 }
         const int inner4 = 4 * R.np, steps4 = (inner4 + 3) / 4;
         for (int t = 0; t < tiles; ++t)
@@ -814,6 +816,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(g.dscale, nd)) != hipSuccess ||
         (e = cd->alloc(g.minv32, size_t(minv32_ptr[h.n_cells]))) != hipSuccess ||
         (e = cd->alloc(w.R32, g.mixed ? nd * nc : 1)) != hipSuccess ||
+        (e = cd->alloc(w.un5, g.mixed ? nd * 5 : 1)) != hipSuccess ||
         (e = cd->alloc(w.x, nd * nc)) != hipSuccess || (e = cd->alloc(w.R, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.S, nd * nc)) != hipSuccess || (e = cd->alloc(w.fprev, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.Sp, g.mixed ? 1 : size_t(afe::kMinvSplitK) * nd * nc)) != hipSuccess ||

@@ -34,6 +34,9 @@ struct DevRef {
     // The same for the mixed-precision contraction, whose inner index has a
     // fourth block: A[m][3 np + p] = M^[m][p], steps = np
     double KMfrag[kRefTiles * kRefNp * 64];
+    // V^ = K^ transposed for the volume term of the corrector, the same
+    // layout: A[m][d np + p] = K^_d[p][m]
+    double Vfrag[kRefTiles * kRefSteps * 64];
     // volume quadrature of the error norms: points, weights (sum 1/6) and
     // basis values phi_m(xi_q) at [q * np + m]
     int nq;
@@ -89,6 +92,7 @@ struct DevWork {
     double *x;       // [ndof][nc] current predictor iterate (final: the solution)
     double *R;       // [ndof][nc] assembled stiffness term (FP64 path)
     float *R32;      // [ndof][nc] mixed: scaled FP32 residual
+    double *un5;     // [ndof][5] mixed: u^n DOF-major (written at the start of each predictor)
     double *S;       // [ndof][nc] M^{-1} R
     double *Sp;      // [4][ndof][nc] FP64: partial products of a split M^{-1} (tail iterations)
     double *rk;      // [nsub][np][nc] per-sub-tet contributions

@@ -531,6 +531,7 @@ __global__ void k_pred_init(DevGrid g, DevWork w, int slot, int32_t *list, int64
             }
         }
     }
+    if (g.mixed && t < g.ndof * 5) w.un5[t] = w.u[(t % 5) * g.ndof + t / 5];  // u^n DOF-major
     const int64_t l = t;
     if (l < g.n_cells) {
         list[base + l] = (slot << kSlotShift) | int32_t(l);
@@ -664,15 +665,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                                                                    int32_t *next_count) {
     using C = Contraction<N, MIXED>;
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
-    constexpr bool QS = VISC || MIXED;  // nodal states shared through LDS
-    constexpr int nd = VISC ? 3 * np * np : 1, sm = MIXED ? spb : 1;
+    constexpr bool QS = VISC;  // nodal states shared through LDS (the viscous gradient)
+    constexpr int nd = VISC ? 3 * np * np : 1;
     constexpr int qsp = QS ? spb : 1, qnt = QS ? nt : 1, qnp = QS ? np : 1;
-    constexpr int mnp = MIXED ? np : 1;
     __shared__ double fT[4 * C::ks][C::ld];  // B operand: f*_d[s][a][p][v] at (d np + p, (s nt + a) 5 + v); g at d = 3
     __shared__ double Dt[nd];                // D^ transposed, as node_flux reads it
     __shared__ double qs[qsp][qnt][qnp][5];  // nodal states
-    __shared__ double us[sm][mnp][5];
-    __shared__ double djs[spb];
     if (blockIdx.x == 0 && threadIdx.x == 0) *next_count = 0;
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
@@ -703,19 +701,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         const int64_t k = s0 + int64_t(chunk) * spb + s;
         const bool valid = node && (k < s1);
         const double dt = *w.dt;
-        double G[9], dj = 0.0, mu_c = 0.0;
+        double G[9], mu_c = 0.0;
         double q[5] = {1, 0, 0, 0, 1};
+        int64_t l = 0;
         if (valid) {
             for (int i = 0; i < 9; ++i) G[i] = g.geo[k * 10 + i];
-            dj = g.geo[k * 10 + 9];
             mu_c = w.mu_cell[c];
-            const int64_t l = g.dof_ptr[c] + g.conn[k * np + m];
+            l = g.dof_ptr[c] + g.conn[k * np + m];
             for (int v = 0; v < 5; ++v) q[v] = w.x[l * nc + a * 5 + v];
             if (QS)
                 for (int v = 0; v < 5; ++v) qs[QS ? s : 0][QS ? a : 0][QS ? m : 0][v] = q[v];
-            if (MIXED && a == 0)
-                for (int v = 0; v < 5; ++v) us[MIXED ? s : 0][MIXED ? m : 0][v] = w.u[v * g.ndof + l];
-            if (a == 0 && m == 0) djs[s] = dj;
         }
         if (QS) __syncthreads();
         if (valid) {
@@ -724,13 +719,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             for (int d = 0; d < 3; ++d)
                 for (int v = 0; v < 5; ++v) fT[d * np + m][(s * nt + a) * 5 + v] = fst[d * 5 + v];
             if (MIXED) {
-                // g_a at node m: the mass term's inner block
+                // g_a at node m: the mass term's inner block, from the node's
+                // row of the iterate (all time nodes) and the DOF-major u^n
                 const double rw = 1.0 / g.ref->w[a];
+                const double *xr = w.x + l * nc;
+                const double *ur = w.un5 + l * 5;
                 for (int v = 0; v < 5; ++v) {
+                    const double un = ur[v];
                     double acc = 0.0;
-                    for (int b = 0; b < nt; ++b)
-                        acc += g.ref->Ktau[a * nt + b] *
-                               (qs[QS ? s : 0][QS ? b : 0][QS ? m : 0][v] - us[MIXED ? s : 0][MIXED ? m : 0][v]);
+                    for (int b = 0; b < nt; ++b) acc += g.ref->Ktau[a * nt + b] * (xr[b * 5 + v] - un);
                     fT[3 * np + m][(s * nt + a) * 5 + v] = rw * acc;
                 }
             }
@@ -758,7 +755,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                     const int ss = col / (nt * 5), aa = (col / 5) % nt, vv = col % 5;
                     const int64_t kk = s0 + int64_t(chunk) * spb + ss;
                     if (kk >= s1) continue;
-                    w.rk[(kk * np + row) * nc + aa * 5 + vv] = g.ref->w[aa] * djs[ss] * acc[mtile][r];
+                    w.rk[(kk * np + row) * nc + aa * 5 + vv] = g.ref->w[aa] * g.geo[kk * 10 + 9] * acc[mtile][r];
                 }
         }
         __syncthreads();  // LDS is rewritten by the next item
@@ -820,23 +817,28 @@ template <int N, int VISC>
 __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevWork w, int which) {
     constexpr int np = Dim<N>::np, nt = Dim<N>::nt, nc = Dim<N>::nc, npt = Dim<N>::npt, spb = Dim<N>::spb;
     constexpr int nf = Dim<N>::nf;
-    __shared__ double Ks[3 * np * np];
+    // the volume term as one product on the matrix cores: rows m, inner
+    // (d, p), columns (sub-tet, variable)
+    constexpr int inner = 3 * np, ks = (inner + 3) / 4, cols = spb * 5, ct = (cols + 15) / 16, ld = 16 * ct;
+    constexpr int mt = (np + 15) / 16;
+    static_assert(kWave * (ct < 4 ? ct : 4) <= Dim<N>::threads, "every wave that takes a column tile is full");
     __shared__ double Dt[VISC ? 3 * np * np : 1];  // D^ transposed, as node_flux reads it
     __shared__ double qs[spb][nt][np][5];
     __shared__ double fs[spb][nt][np][15];  // f*, then (once fbar is formed) the physical fluxes F
-    __shared__ double fbar[spb][np][15];
-    const int tid = threadIdx.x;
+    __shared__ double fbT[4 * ks][ld];      // B operand: Fbar*_d[s][p][v] at (d np + p, s 5 + v)
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
     const int s = tid / npt, a = (tid / np) % nt, m = tid % np;
     const int64_t k = int64_t(blockIdx.x) * spb + s;
     const int c = (s < spb) && (k < g.nsub) ? g.sub_cell[k] : -1;
     const bool valid = c >= 0 && w.late[c] == which;
     // the later passes have few cells: blocks without one leave before loading anything
     if (!__syncthreads_or(valid)) return;
-    for (int t = tid; t < 3 * np * np; t += blockDim.x) {
-        Ks[t] = g.ref->K[t];
-        const int d = t / (np * np), mm = (t / np) % np, p = t % np;
-        if (VISC) Dt[VISC ? (d * np + p) * np + mm : 0] = g.ref->D[t];
-    }
+    for (int t = tid; t < 4 * ks * ld; t += blockDim.x) fbT[t / ld][t % ld] = 0.0;  // padding stays zero
+    if (VISC)
+        for (int t = tid; t < 3 * np * np; t += blockDim.x) {
+            const int d = t / (np * np), mm = (t / np) % np, p = t % np;
+            Dt[VISC ? (d * np + p) * np + mm : 0] = g.ref->D[t];
+        }
     const double dt = *w.dt;
     double G[9], dj = 0.0, mu_c = 0.0;
     double q[5] = {1, 0, 0, 0, 1};
@@ -854,31 +856,50 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
     double F[3][5];
     if (valid) node_flux<N, VISC>(Dt, qs[s][a], m, G, q, g.gamma, mu_c, g.kappa, g.cv, dt, fs[s][a][m], F);
     __syncthreads();
-    if (valid && a == 0) {
-        for (int i = 0; i < 15; ++i) {
+    // time averages Fbar*_{d}[m][v] = sum_b w_b f*_d[b][m][v], the 15 entries
+    // of a node split over its nt threads
+    if (valid)
+        for (int i = a; i < 15; i += nt) {
             double acc = 0.0;
             for (int b = 0; b < nt; ++b) acc += g.ref->w[b] * fs[s][b][m][i];
-            fbar[s][m][i] = acc;
+            fbT[(i / 5) * np + m][s * 5 + i % 5] = acc;
         }
-    }
     __syncthreads();
     if (valid)
         for (int x = 0; x < 3; ++x)
             for (int v = 0; v < 5; ++v) fs[s][a][m][x * 5 + v] = F[x][v];
     __syncthreads();
-    if (!valid) return;
-    if (a == 0) {
-        // volume term: V^_d[m][p] = K^_d[p][m]
-        double r[5] = {0, 0, 0, 0, 0};
-        for (int d = 0; d < 3; ++d)
-            for (int p = 0; p < np; ++p) {
-                const double kk = Ks[(d * np + p) * np + m];
-                for (int v = 0; v < 5; ++v) r[v] += kk * fbar[s][p][d * 5 + v];
+    // volume term vk[k][m][v] = |J_k| sum_d sum_p V^_d[m][p] Fbar*_d[p][v], V^_d[m][p] = K^_d[p][m]
+    const int64_t k0 = int64_t(blockIdx.x) * spb;
+    const gptr<double> Vf = (gptr<double>)uni_ptr(g.ref->Vfrag) + lane;
+    for (int ctile = wv; ctile < ct; ctile += 4) {
+        dbl4 acc[mt];
+#pragma unroll
+        for (int mtile = 0; mtile < mt; ++mtile) acc[mtile] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kst = 0; kst < ks; ++kst) {
+            const double bv = fbT[4 * kst + mf_b_k(lane)][16 * ctile + mf_b_col(lane)];
+#pragma unroll
+            for (int mtile = 0; mtile < mt; ++mtile)
+                acc[mtile] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vf[(mtile * ks + kst) * kWave], bv, acc[mtile], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mtile = 0; mtile < mt; ++mtile)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * mtile + mf_d_row(lane, r), col = 16 * ctile + mf_d_col(lane, r);
+                if (row >= np || col >= cols) continue;
+                const int ss = col / 5, vv = col % 5;
+                const int64_t kk = k0 + ss;
+                if (kk >= g.nsub) continue;
+                const int cc = g.sub_cell[kk];
+                if (w.late[cc] != which) continue;
+                w.vk[(kk * np + row) * 5 + vv] = g.geo[kk * 10 + 9] * acc[mtile][r];
             }
-        double *out = w.vk + (k * np + m) * 5;
-        for (int v = 0; v < 5; ++v) out[v] = dj * r[v];
-    } else if (a == 1 || nt == 1) {
-        // traces at face nodes (threads of time node 1 are free here)
+    }
+    if (!valid) return;
+    if (a == 1 || nt == 1) {
+        // traces at face nodes
         if (m < nf) {
             const int j = m, mm = g.ref->fn[j];
             double *out = w.trace + (k * nf + j) * 20;
