@@ -630,6 +630,16 @@ __device__ inline int mf_d_row(int l, int r) { return l / 16 + 4 * r; }
 __device__ inline int mf_d_col(int l, int) { return l % 16; }
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// Column of element (row, col) of an LDS B operand: the low 4 bits of the
+// column are XORed with the row's, and (PAIR, rows of 32 k doubles) odd rows
+// swap neighbouring 16-column tiles.  Writes down a column (one row per
+// lane) then fall in distinct banks, and with PAIR the MFMA read of 4 rows x
+// 16 columns spreads over both halves of the banks.
+template <bool PAIR>
+__device__ inline int lds_swz(int row, int col) { return col ^ (row & 15) ^ (PAIR ? ((row & 1) << 4) : 0); }
+// B-operand row length for ct column tiles: whole tile pairs when there are two or more
+__host__ __device__ constexpr int lds_ld(int ct) { return ct >= 2 ? 32 * ((ct + 1) / 2) : 16 * ct; }
+
 // Shape of the chunk's stiffness contraction as one matrix product:
 // rows = node m, inner index = (d, p), columns = (sub-tet, time node, variable);
 // in mixed precision a fourth inner block d = 3 carries the mass term.
@@ -641,7 +651,8 @@ struct Contraction {
     static constexpr int cols = Dim<N>::spb * Dim<N>::nt * 5;
     static constexpr int ct = (cols + 15) / 16;  // column tiles
     static constexpr int mt = (np + 15) / 16;    // row tiles
-    static constexpr int ld = 16 * ct;           // row stride of the B operand in LDS
+    static constexpr int ld = lds_ld(ct);        // row stride of the B operand in LDS
+    static constexpr bool pair = ct >= 2;        // lds_swz variant
 };
 
 // Work item = (entry, chunk of spb sub-tets of the cell), 256 threads.  Per
@@ -717,7 +728,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             double F[3][5], fst[15];
             node_flux<N, VISC>(Dt, qs[QS ? s : 0][QS ? a : 0], m, G, q, g.gamma, mu_c, g.kappa, g.cv, dt, fst, F);
             for (int d = 0; d < 3; ++d)
-                for (int v = 0; v < 5; ++v) fT[d * np + m][(s * nt + a) * 5 + v] = fst[d * 5 + v];
+                for (int v = 0; v < 5; ++v) fT[d * np + m][lds_swz<C::pair>(d * np + m, (s * nt + a) * 5 + v)] = fst[d * 5 + v];
             if (MIXED) {
                 // g_a at node m: the mass term's inner block, from the node's
                 // row of the iterate (all time nodes) and the DOF-major u^n
@@ -728,7 +739,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                     const double un = ur[v];
                     double acc = 0.0;
                     for (int b = 0; b < nt; ++b) acc += g.ref->Ktau[a * nt + b] * (xr[b * 5 + v] - un);
-                    fT[3 * np + m][(s * nt + a) * 5 + v] = rw * acc;
+                    fT[3 * np + m][lds_swz<C::pair>(3 * np + m, (s * nt + a) * 5 + v)] = rw * acc;
                 }
             }
         }
@@ -740,7 +751,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             for (int mtile = 0; mtile < C::mt; ++mtile) acc[mtile] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kst = 0; kst < C::ks; ++kst) {
-                const double bv = fT[4 * kst + mf_b_k(lane)][16 * ctile + mf_b_col(lane)];
+                const int br = 4 * kst + mf_b_k(lane);
+                const double bv = fT[br][lds_swz<C::pair>(br, 16 * ctile + mf_b_col(lane))];
 #pragma unroll
                 for (int mtile = 0; mtile < C::mt; ++mtile)
                     acc[mtile] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kf[(mtile * C::ks + kst) * kWave], bv, acc[mtile], 0,
@@ -819,7 +831,9 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
     constexpr int nf = Dim<N>::nf;
     // the volume term as one product on the matrix cores: rows m, inner
     // (d, p), columns (sub-tet, variable)
-    constexpr int inner = 3 * np, ks = (inner + 3) / 4, cols = spb * 5, ct = (cols + 15) / 16, ld = 16 * ct;
+    constexpr int inner = 3 * np, ks = (inner + 3) / 4, cols = spb * 5, ct = (cols + 15) / 16;
+    constexpr int ld = lds_ld(ct);
+    constexpr bool pair = ct >= 2;
     constexpr int mt = (np + 15) / 16;
     static_assert(kWave * (ct < 4 ? ct : 4) <= Dim<N>::threads, "every wave that takes a column tile is full");
     __shared__ double Dt[VISC ? 3 * np * np : 1];  // D^ transposed, as node_flux reads it
@@ -862,7 +876,7 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
         for (int i = a; i < 15; i += nt) {
             double acc = 0.0;
             for (int b = 0; b < nt; ++b) acc += g.ref->w[b] * fs[s][b][m][i];
-            fbT[(i / 5) * np + m][s * 5 + i % 5] = acc;
+            fbT[(i / 5) * np + m][lds_swz<pair>((i / 5) * np + m, s * 5 + i % 5)] = acc;
         }
     __syncthreads();
     if (valid)
@@ -878,7 +892,8 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
         for (int mtile = 0; mtile < mt; ++mtile) acc[mtile] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int kst = 0; kst < ks; ++kst) {
-            const double bv = fbT[4 * kst + mf_b_k(lane)][16 * ctile + mf_b_col(lane)];
+            const int br = 4 * kst + mf_b_k(lane);
+            const double bv = fbT[br][lds_swz<pair>(br, 16 * ctile + mf_b_col(lane))];
 #pragma unroll
             for (int mtile = 0; mtile < mt; ++mtile)
                 acc[mtile] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vf[(mtile * ks + kst) * kWave], bv, acc[mtile], 0, 0, 0);
