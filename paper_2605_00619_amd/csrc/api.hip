@@ -194,6 +194,10 @@ namespace {
 // afe_params.history_cells.
 int hist_small_of(int depth, int history_cells) { return history_cells > 0 ? std::min(depth, 8) : depth; }
 
+// Doubles to allocate for `values` history entries: FP64, or FP32 in mixed
+// precision (two per double).
+size_t hist_doubles(size_t values, bool mixed) { return mixed ? (values + 1) / 2 : values; }
+
 size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub, int max_cell_dofs, int depth,
                       bool mixed, int history_cells) {
     const size_t nc = size_t(5) * (N + 1);
@@ -206,9 +210,10 @@ size_t estimate_bytes(int N, const std::vector<int64_t> &cell_dofs, int64_t nsub
         ndof += size_t(n);
     }
     const int hs = hist_small_of(depth, history_cells);
-    b += ndof * nc * sizeof(double) * (5 + 2 * size_t(std::max(hs, 1)));
-    if (hs < depth)
-        b += 2 * size_t(history_cells) * size_t(depth - hs) * size_t(max_cell_dofs) * nc * sizeof(double);
+    b += ndof * nc * sizeof(double) * 5;  // x, R, S, f, G(x)
+    b += 2 * hist_doubles(ndof * nc * size_t(std::max(hs, 1)), mixed) * sizeof(double);  // in-place history
+    b += 2 * hist_doubles(hs < depth ? size_t(history_cells) * size_t(depth - hs) * size_t(max_cell_dofs) * nc : 1,
+                          mixed) * sizeof(double);  // pooled history
     if (mixed) b += ndof * nc * sizeof(float) + ndof * 5 * sizeof(double);  // FP32 residual, u^n DOF-major
     else b += size_t(afe::kMinvSplitK) * ndof * nc * sizeof(double);  // split M^-1 partials
     b += n_cells * size_t((max_cell_dofs + 63) / 64) * 130 * sizeof(double);
@@ -822,9 +827,11 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
         (e = cd->alloc(w.Sp, g.mixed ? 1 : size_t(afe::kMinvSplitK) * nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.gprev, nd * nc)) != hipSuccess ||
         (e = cd->alloc(w.part, size_t(h.n_cells) * ((h.max_cell_dofs + 63) / 64) * 130)) != hipSuccess ||
-        (e = cd->alloc(w.dF, nd * nc * dslots)) != hipSuccess ||
-        (e = cd->alloc(w.dG, nd * nc * dslots)) != hipSuccess || (e = cd->alloc(w.dFp, pool)) != hipSuccess ||
-        (e = cd->alloc(w.dGp, pool)) != hipSuccess || (e = cd->alloc(w.pool_slot, size_t(h.n_cells))) != hipSuccess ||
+        (e = cd->alloc(w.dF, hist_doubles(nd * nc * dslots, g.mixed))) != hipSuccess ||
+        (e = cd->alloc(w.dG, hist_doubles(nd * nc * dslots, g.mixed))) != hipSuccess ||
+        (e = cd->alloc(w.dFp, hist_doubles(pool, g.mixed))) != hipSuccess ||
+        (e = cd->alloc(w.dGp, hist_doubles(pool, g.mixed))) != hipSuccess ||
+        (e = cd->alloc(w.pool_slot, size_t(h.n_cells))) != hipSuccess ||
         (e = cd->alloc(w.pool_count, 1)) != hipSuccess ||
         (e = cd->alloc(w.gram, size_t(h.n_cells) * (2 * 63 * 63 + 63))) != hipSuccess ||
         (e = cd->alloc(w.hist, size_t(h.n_cells) * 2)) != hipSuccess ||

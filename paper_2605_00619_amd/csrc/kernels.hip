@@ -1159,11 +1159,15 @@ constexpr int kDrop = 8;
 constexpr int kPartStride = 2 * (kMaxDepth + 1) + 2;
 
 // Column of ring slot s of cell c in a history area (dF or dG): in place for
-// s < hist_small, else in the cell's pool slot.
-__device__ inline double *hist_col(const DevGrid &g, const DevWork &w, double *in_place, double *pool, int c,
-                                   int64_t base, int64_t len, int s) {
-    if (s < g.hist_small) return in_place + base * g.hist_small + int64_t(s) * len;
-    return pool + int64_t(w.pool_slot[c]) * g.pool_stride + int64_t(s - g.hist_small) * len;
+// s < hist_small, else in the cell's pool slot.  HT is the element type of
+// the history: double, or float in mixed precision (the same areas, read as
+// floats).
+template <typename HT>
+__device__ inline HT *hist_col(const DevGrid &g, const DevWork &w, double *in_place, double *pool, int c,
+                               int64_t base, int64_t len, int s) {
+    HT *ip = reinterpret_cast<HT *>(in_place), *pl = reinterpret_cast<HT *>(pool);
+    if (s < g.hist_small) return ip + base * g.hist_small + int64_t(s) * len;
+    return pl + int64_t(w.pool_slot[c]) * g.pool_stride + int64_t(s - g.hist_small) * len;
 }
 
 // history bookkeeping: (count kept, head slot) after the drop this iteration makes
@@ -1189,7 +1193,7 @@ __device__ inline int part_tiles(const DevGrid &g) { return (g.max_cell_dofs + 6
 constexpr int kDotCols = 4;
 constexpr int kDotColsWide = 16;
 
-template <int N, int DC>
+template <int N, int DC, typename HT>
 __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, int tile, double (*accs)[4]) {
     constexpr int nc = Dim<N>::nc, nt = Dim<N>::nt;
     constexpr int kPer = (64 * nc + 255) / 256;  // elements per thread
@@ -1251,10 +1255,11 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
             fmx = fmax(fmx, fabs(fv));
             gmx = fmax(gmx, fabs(gv));
             if (hist_on) {
-                const double dfn = fv - w.fprev[base + e];
-                hist_col(g, w, w.dF, w.dFp, c, base, len, snew)[e] = dfn;
-                hist_col(g, w, w.dG, w.dGp, c, base, len, snew)[e] = gv - w.gprev[base + e];
-                dfe[q] = dfn;
+                // the column as stored (rounded to HT) enters the dot products too
+                const HT dfn = HT(fv - w.fprev[base + e]);
+                hist_col<HT>(g, w, w.dF, w.dFp, c, base, len, snew)[e] = dfn;
+                hist_col<HT>(g, w, w.dG, w.dGp, c, base, len, snew)[e] = HT(gv - w.gprev[base + e]);
+                dfe[q] = double(dfn);
             }
             fe[q] = fv;
             w.fprev[base + e] = fv;
@@ -1281,7 +1286,8 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
 #pragma unroll
                     for (int u = 0; u < DC; ++u) {
                         const int j = j0 + u;
-                        d[u] = j < k ? hist_col(g, w, w.dF, w.dFp, c, base, len, (head + j) % depth)[ie[q]] : dfe[q];
+                        d[u] = j < k ? double(hist_col<HT>(g, w, w.dF, w.dFp, c, base, len, (head + j) % depth)[ie[q]])
+                                     : dfe[q];
                     }
 #pragma unroll
                     for (int u = 0; u < DC; ++u) {
@@ -1499,7 +1505,7 @@ __device__ inline void and_solve_cell(const DevGrid &g, const DevWork &w, int c,
     __syncthreads();  // Ls is reused by the next item
 }
 
-template <int N, int DC>
+template <int N, int DC, typename HT>
 __global__ void __launch_bounds__(256) k_round_dots(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
                                                     const int32_t *__restrict__ count, int tpc) {
     __shared__ double accs[kPartStride][4];
@@ -1511,7 +1517,7 @@ __global__ void __launch_bounds__(256) k_round_dots(const DevSlot *__restrict__ 
         const DevWork &w = tab[slot].w;
         const int tile = item % tpc;
         if (tile * 64 >= int(g.dof_ptr[c + 1] - g.dof_ptr[c])) continue;
-        and_dots_tile<N, DC>(g, w, c, tile, accs);
+        and_dots_tile<N, DC, HT>(g, w, c, tile, accs);
         __syncthreads();  // accs is rewritten by the next item
     }
 }
@@ -1536,7 +1542,7 @@ constexpr int kUpdBatch = 8;
 // last iterations, with few cells left and long histories, a cell's history
 // columns are read by five times as many waves.  Each value's arithmetic is
 // the same either way.
-template <int N>
+template <int N, typename HT>
 __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict__ tab, const int32_t *__restrict__ list,
                                                       const int32_t *__restrict__ count, int per, int fine) {
     constexpr int nc = Dim<N>::nc;
@@ -1564,11 +1570,11 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
                 double d[kUpdBatch];
 #pragma unroll
                 for (int u = 0; u < kUpdBatch; ++u)
-                    d[u] = hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j + u) % depth)[e];
+                    d[u] = double(hist_col<HT>(g, w, w.dG, w.dGp, c, base, len, (head + j + u) % depth)[e]);
 #pragma unroll
                 for (int u = 0; u < kUpdBatch; ++u) xv -= gam[j + u] * d[u];
             }
-            for (; j < kuse; ++j) xv -= gam[j] * hist_col(g, w, w.dG, w.dGp, c, base, len, (head + j) % depth)[e];
+            for (; j < kuse; ++j) xv -= gam[j] * double(hist_col<HT>(g, w, w.dG, w.dGp, c, base, len, (head + j) % depth)[e]);
             w.x[base + e] = xv;
         }
     }
@@ -1946,13 +1952,17 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
             hipLaunchKernelGGL(k_round_minv<D::nc>, grid(a.shape.g_minv, tpc * a.split), dim3(256), 0, s, a.tab,
                                a.list, a.count, tpc, a.split, a.bytes);
         if (a.ev1) (void)hipEventRecord(a.ev1, s);
-        auto dots = a.upd_fine && a.n_upper >= 0 ? k_round_dots<NN, kDotColsWide> : k_round_dots<NN, kDotCols>;
+        auto dots = a.mixed ? (a.upd_fine && a.n_upper >= 0 ? k_round_dots<NN, kDotColsWide, float>
+                                                           : k_round_dots<NN, kDotCols, float>)
+                            : (a.upd_fine && a.n_upper >= 0 ? k_round_dots<NN, kDotColsWide, double>
+                                                           : k_round_dots<NN, kDotCols, double>);
         hipLaunchKernelGGL(dots, grid(a.shape.g_dots, tpc), dim3(256), 0, s, a.tab, a.list, a.count, tpc);
         hipLaunchKernelGGL(k_round_solve, grid(a.shape.g_solve, 1), dim3(kWave), 0, s, a.tab, a.list, a.count, a.next,
                            a.next_count);
         const int upd_per = a.upd_fine ? per : tpc;
-        hipLaunchKernelGGL(k_round_update<NN>, grid(a.shape.g_update, upd_per), dim3(256), 0, s, a.tab, a.list,
-                           a.count, upd_per, a.upd_fine);
+        auto upd = a.mixed ? k_round_update<NN, float> : k_round_update<NN, double>;
+        hipLaunchKernelGGL(upd, grid(a.shape.g_update, upd_per), dim3(256), 0, s, a.tab, a.list, a.count, upd_per,
+                           a.upd_fine);
         return hipGetLastError();
     });
 }
@@ -2053,9 +2063,11 @@ IterShape resident_shape(int N, int mixed, int visc) {
         sh.g_gather = fit(reinterpret_cast<const void *>(&k_round_gather<NN>), 256);
         sh.g_minv = mixed ? fit(reinterpret_cast<const void *>(&k_round_minv32<D::nc>), 256)
                           : fit(reinterpret_cast<const void *>(&k_round_minv<D::nc>), 256);
-        sh.g_dots = fit(reinterpret_cast<const void *>(&k_round_dots<NN, kDotCols>), 256);
+        sh.g_dots = mixed ? fit(reinterpret_cast<const void *>(&k_round_dots<NN, kDotCols, float>), 256)
+                          : fit(reinterpret_cast<const void *>(&k_round_dots<NN, kDotCols, double>), 256);
         sh.g_solve = fit(reinterpret_cast<const void *>(&k_round_solve), kWave);
-        sh.g_update = fit(reinterpret_cast<const void *>(&k_round_update<NN>), 256);
+        sh.g_update = mixed ? fit(reinterpret_cast<const void *>(&k_round_update<NN, float>), 256)
+                            : fit(reinterpret_cast<const void *>(&k_round_update<NN, double>), 256);
         return hipSuccess;
     });
     return sh;
