@@ -100,3 +100,76 @@ def affine_density(x: np.ndarray, t: float = 0.0, grad=(0.05, -0.03, 0.02), rho0
     out[:, 1:4] = vel
     out[:, 4] = p0
     return out
+
+
+def shear_heating(x: np.ndarray, t: float = 0.0, a: float = 0.3, x0: float = 0.5, p0: float = 1.0,
+                  mu: float = 0.01, gamma: float = 1.4) -> np.ndarray:
+    """rho = 1, v = (0, a (x - x0), 0), p = p0 + (gamma - 1) mu a^2 t: a linear
+    shear flow whose viscous dissipation heats the gas uniformly, an exact
+    solution of the compressible Navier-Stokes equations (the stress is
+    constant, the temperature uniform in space)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros((len(x), 5))
+    out[:, 0] = 1.0
+    out[:, 2] = a * (x[:, 0] - x0)
+    out[:, 4] = p0 + (gamma - 1.0) * mu * a * a * t
+    return out
+
+
+def shear_heating_grad(x: np.ndarray, t: float = 0.0, a: float = 0.3, **_) -> np.ndarray:
+    """Gradient of shear_heating's primitive variables, [n, 3, 5] with
+    [.., d, k] = d prim_k / d x_d."""
+    g = np.zeros((len(x), 3, 5))
+    g[:, 0, 2] = a
+    return g
+
+
+def stokes_first(x: np.ndarray, t: float = 0.0, nu: float = 1e-3, vl: float = 0.1, vr: float = -0.1,
+                 t0: float = 0.05, gamma: float = 1.4) -> np.ndarray:
+    """First problem of Stokes (Sec. 5.3): rho = 1, p = 1/gamma, u = w = 0,
+    v = (vl + vr)/2 + (vr - vl)/2 erf((x - 1/2) / (2 sqrt(nu (t + t0)))), the
+    incompressible shear-layer solution."""
+    from scipy.special import erf
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros((len(x), 5))
+    out[:, 0] = 1.0
+    out[:, 2] = 0.5 * (vl + vr) + 0.5 * (vr - vl) * erf((x[:, 0] - 0.5) / (2.0 * math.sqrt(nu * (t + t0))))
+    out[:, 4] = 1.0 / gamma
+    return out
+
+
+def stokes_first_grad(x: np.ndarray, t: float = 0.0, nu: float = 1e-3, vl: float = 0.1, vr: float = -0.1,
+                      t0: float = 0.05, **_) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    s = 2.0 * math.sqrt(nu * (t + t0))
+    g = np.zeros((len(x), 3, 5))
+    g[:, 0, 2] = 0.5 * (vr - vl) * 2.0 / math.sqrt(math.pi) * np.exp(-((x[:, 0] - 0.5) / s) ** 2) / s
+    return g
+
+
+def taylor_green_2d(x: np.ndarray, t: float = 0.0, nu: float = 1e-2, p0: float = 100.0) -> np.ndarray:
+    """Two-dimensional Taylor-Green vortex (Sec. 5.5): rho = 1,
+    u = sin x cos y e^(-2 nu t), v = -cos x sin y e^(-2 nu t), w = 0,
+    p = p0 / gamma + (cos 2x + cos 2y) e^(-4 nu t) / 4 with gamma = 1.4 (the
+    incompressible solution; p0 = 100 puts the Mach number near 0.1)."""
+    x = np.asarray(x, dtype=np.float64)
+    f = math.exp(-2.0 * nu * t)
+    out = np.zeros((len(x), 5))
+    out[:, 0] = 1.0
+    out[:, 1] = np.sin(x[:, 0]) * np.cos(x[:, 1]) * f
+    out[:, 2] = -np.cos(x[:, 0]) * np.sin(x[:, 1]) * f
+    out[:, 4] = p0 / 1.4 + 0.25 * (np.cos(2 * x[:, 0]) + np.cos(2 * x[:, 1])) * f * f
+    return out
+
+
+def taylor_green_2d_grad(x: np.ndarray, t: float = 0.0, nu: float = 1e-2, **_) -> np.ndarray:
+    x = np.asarray(x, dtype=np.float64)
+    f = math.exp(-2.0 * nu * t)
+    g = np.zeros((len(x), 3, 5))
+    g[:, 0, 1] = np.cos(x[:, 0]) * np.cos(x[:, 1]) * f
+    g[:, 1, 1] = -np.sin(x[:, 0]) * np.sin(x[:, 1]) * f
+    g[:, 0, 2] = np.sin(x[:, 0]) * np.sin(x[:, 1]) * f
+    g[:, 1, 2] = -np.cos(x[:, 0]) * np.cos(x[:, 1]) * f
+    g[:, 0, 4] = -0.5 * np.sin(2 * x[:, 0]) * f * f
+    g[:, 1, 4] = -0.5 * np.sin(2 * x[:, 1]) * f * f
+    return g

@@ -58,8 +58,10 @@ R21 (Dirichlet boundaries, Sec. 5.1-5.2 "Dirichlet boundary conditions on all
    and Fbar+ = dt sum_a w_a F(q_e(a)); the Rusanov flux of R5 is then taken
    as at an interior triangle, with the "+" wave speeds from qbar+ / dt.  The
    detector (R6) counts no velocity jump and no outside sound speed across a
-   boundary triangle.  Boundaries are taken for the Euler equations only
-   (mu = kappa = 0, no artificial viscosity).
+   boundary triangle.  With viscosity or heat conduction the "+" flux is the
+   Navier-Stokes flux of the exact state with the exact solution's gradient
+   (given with the data) and the inside cell's viscosity; the penalty of R5
+   takes the inside cell's viscosity and length scale on both sides.
 """
 from __future__ import annotations
 
@@ -135,17 +137,19 @@ class Oracle:
     neighbours when artificial viscosity is on, are built as needed).
     """
 
-    def __init__(self, mesh: dict, N: int, params: Params = Params(), cells=None, boundary=None):
+    def __init__(self, mesh: dict, N: int, params: Params = Params(), cells=None, boundary=None,
+                 boundary_grad=None):
         self.mesh = mesh
         self.N = N
         self.p = params
         # exact solution for the Dirichlet data of a bounded mesh (R21):
-        # boundary(x [n, 3], t) -> primitive (rho, u, v, w, p) [n, 5]
+        # boundary(x [n, 3], t) -> primitive (rho, u, v, w, p) [n, 5]; with
+        # viscosity or heat conduction also boundary_grad(x, t) -> its
+        # gradient [n, 3, 5], [.., d, k] = d prim_k / d x_d
         self.bounded = bool(mesh.get("bounded", False))
         self.boundary = boundary
+        self.boundary_grad = boundary_grad
         self.t = 0.0
-        if self.bounded and (params.mu != 0.0 or params.kappa != 0.0 or params.av):
-            raise ValueError("boundaries are taken for the Euler equations only (R21)")
         self.ref = ref_element(N)
         self.tb = time_basis(N)
         n = mesh["n_cells"]
@@ -352,8 +356,8 @@ class Oracle:
         nb = int(g.nbr[k])
         qi, Fi = ti[c]["tq"][k], ti[c]["tF"][k]
         if nb < 0:
-            qo, Fo = self.boundary_traces(c, k, dt)
-            nb = c  # viscosity and length scale of the inside (mu = 0 here, R21)
+            qo, Fo = self.boundary_traces(c, k, dt, mus[c])
+            nb = c  # viscosity and length scale of the inside (R21)
         else:
             kn = int(g.nbr_tri[k])
             perm = g.nbr_perm[k]
@@ -370,16 +374,38 @@ class Oracle:
         s = lam + 2.0 * eps * lamv
         return 0.5 * np.einsum("jxv,x->jv", Fo + Fi, n) - 0.5 * s * (qo - qi)
 
-    def boundary_traces(self, c: int, k: int, dt: float):
+    def boundary_traces(self, c: int, k: int, dt: float, mu: float = 0.0):
         """qbar+ [nf, 5] and Fbar+ [nf, 3, 5] of the exact solution at the face
-        nodes of cell c's boundary triangle k over the step (R21)."""
+        nodes of cell c's boundary triangle k over the step (R21); mu is the
+        inside cell's viscosity."""
         if self.boundary is None:
             raise ValueError("a bounded mesh needs the exact solution for its boundary data")
         g = self.grids[c]
         x = g.dof_x[g.face_dof[k]]
-        qa = np.stack([prim_to_cons(self.boundary(x, self.t + tau * dt), self.p.gamma) for tau in self.tb.tau])
+        gam = self.p.gamma
+        viscous = mu != 0.0 or self.p.kappa != 0.0
+        if viscous and self.boundary_grad is None:
+            raise ValueError("viscous boundary data need the exact solution's gradient")
+        qs, Fs = [], []
+        for tau in self.tb.tau:
+            t = self.t + tau * dt
+            w = self.boundary(x, t)
+            q = prim_to_cons(w, gam)
+            gq = None
+            if viscous:
+                # d(conserved)/dx from d(primitive)/dx: rho, rho v, rho E = p/(gamma-1) + rho |v|^2 / 2
+                gw = self.boundary_grad(x, t)  # [nf, 3, 5]
+                rho, vel = w[:, 0], w[:, 1:4]
+                gq = np.empty_like(gw)
+                gq[..., 0] = gw[..., 0]
+                gq[..., 1:4] = vel[:, None, :] * gw[..., :1] + rho[:, None, None] * gw[..., 1:4]
+                gq[..., 4] = (gw[..., 4] / (gam - 1.0) + 0.5 * (vel * vel).sum(-1)[:, None] * gw[..., 0]
+                              + rho[:, None] * np.einsum("ni,ndi->nd", vel, gw[..., 1:4]))
+            qs.append(q)
+            Fs.append(flux(q, gam, mu, gq, self.p.kappa, self.p.cv))
+        qa, Fa = np.stack(qs), np.stack(Fs)
         qbar = dt * np.einsum("a,ajv->jv", self.tb.w, qa)
-        Fbar = dt * np.einsum("a,ajxv->jxv", self.tb.w, flux(qa, self.p.gamma))
+        Fbar = dt * np.einsum("a,ajxv->jxv", self.tb.w, Fa)
         return qbar, Fbar
 
     def face_term(self, c: int, ti: dict, mus: dict, dt: float) -> np.ndarray:

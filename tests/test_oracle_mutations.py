@@ -8,7 +8,8 @@ CPU), points the pin test at the changed module and expects the pin to fail:
 - the face mass matrix Z^ lumped to its row sums (Sec. 4.4),
 - the time weights w_a dropped from the predictor's stiffness term (eq:ader4),
 - the boundary data taken at the start of the step instead of at the time
-  nodes, or with the "+" side's own face nodes reversed (R21).
+  nodes, or with the "+" side's own face nodes reversed, or the exact
+  gradient left out of the viscous boundary flux (R21).
 """
 import importlib.util
 import os
@@ -94,7 +95,7 @@ def test_dropped_time_weights_are_caught(monkeypatch, mesh3):
 
 
 BOUNDARY = [
-    ("boundary data at t^n", "self.boundary(x, self.t + tau * dt)", "self.boundary(x, self.t + 0.0 * tau * dt)"),
+    ("boundary data at t^n", "t = self.t + tau * dt", "t = self.t + 0.0 * tau * dt"),
     ("boundary face nodes reversed", "x = g.dof_x[g.face_dof[k]]", "x = g.dof_x[g.face_dof[k]][::-1]"),
 ]
 
@@ -106,3 +107,12 @@ def test_boundary_mutation_is_caught(monkeypatch, name, old, new):
     monkeypatch.setattr(boundary_pins, "Oracle", mod.Oracle)
     with pytest.raises(AssertionError):
         boundary_pins.test_affine_solution_reproduced_with_boundary_data(2)
+
+
+def test_dropped_boundary_gradient_is_caught(monkeypatch):
+    """The viscous pin sees the gradient of the boundary data."""
+    boundary_pins.test_viscous_shear_reproduced_with_boundary_data(0.0)
+    mod = _mutated("scheme", "gw = self.boundary_grad(x, t)  # [nf, 3, 5]", "gw = 0.0 * self.boundary_grad(x, t)")
+    monkeypatch.setattr(boundary_pins, "Oracle", mod.Oracle)
+    with pytest.raises(AssertionError):
+        boundary_pins.test_viscous_shear_reproduced_with_boundary_data(0.0)
