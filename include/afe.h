@@ -160,7 +160,8 @@ afe_status afe_connectivity(const afe_cell_data *cd, int64_t *subtet_ptr, int32_
  * on all sides).  A boundary triangle's outside state in the Rusanov flux of
  * Sec. 4.4 is the given solution at its face nodes at the predictor's time
  * nodes t^n + tau_a dt: qbar = dt sum_a w_a q_a and Fbar = dt sum_a w_a F(q_a)
- * (Euler flux); the detector of Sec. 4.5 counts no velocity jump across it.
+ * (Euler flux, or Navier-Stokes flux with the given gradient, below); the
+ * detector of Sec. 4.5 counts no velocity jump across it.
  * afe_boundary_nodes writes *count = (boundary triangles) * nf, the boundary
  * face nodes (triangle b's face node j is node b * nf + j, triangles in
  * ascending sub-tet order), and, when not NULL, their coordinates xyz host
@@ -170,12 +171,18 @@ afe_status afe_connectivity(const afe_cell_data *cd, int64_t *subtet_ptr, int32_
  * next step; caller-owned, read by every following ader_step, ader_correct
  * and ader_step_noalloc, so the caller refills it (for the new t^n and dt)
  * before each step; NULL unregisters.  A step of a bounded object without
- * registered states fails with AFE_E_ARG.  Bounded objects take the Euler
- * equations only (build_afe_cell_data fails with AFE_E_ARG for mu, kappa or
- * av) and are stepped alone with the caller's dt (afe_batch_attach fails with
- * AFE_E_ARG).  Errors: AFE_E_ARG. */
+ * registered states fails with AFE_E_ARG.  With viscosity, heat conduction
+ * or artificial viscosity the outside flux is the Navier-Stokes flux of the
+ * given state with its gradient and the inside cell's viscosity:
+ * afe_set_boundary_gradients registers grad, device [count][N+1][3][5], the
+ * gradient d prim_k / d x_d of the primitive state at each boundary node and
+ * time node (same ownership and refill rule); a viscous step of a bounded
+ * object without it fails with AFE_E_ARG.  Bounded objects are stepped alone
+ * with the caller's dt (afe_batch_attach fails with AFE_E_ARG).
+ * Errors: AFE_E_ARG. */
 afe_status afe_boundary_nodes(const afe_cell_data *cd, int64_t *count, double *xyz, double *tau);
 afe_status afe_set_boundary_states(afe_cell_data *cd, const double *prim);
+afe_status afe_set_boundary_gradients(afe_cell_data *cd, const double *grad);
 
 /* Host-only construction of the same sub-grid (no device memory, no GPU):
  * afe_subgrid_sizes returns sizes[0] = number of sub-tets, sizes[1] = number

@@ -32,7 +32,7 @@ EXPORTED = [
     "afe_batch_create", "afe_batch_free", "afe_batch_attach", "afe_batch_detach", "afe_batch_step",
     "afe_batch_set_shape", "afe_batch_get_shape", "afe_batch_tune", "afe_batch_profile_enable",
     "afe_batch_profile_read", "ader_step_noalloc", "afe_l2_points", "afe_l2_error",
-    "afe_boundary_nodes", "afe_set_boundary_states",
+    "afe_boundary_nodes", "afe_set_boundary_states", "afe_set_boundary_gradients",
 ]
 BATCH_SLOTS = 64
 
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "afe_l2_error": ([vp, vp, i32, vp, ctypes.POINTER(dbl), vp], i32),
         "afe_boundary_nodes": ([vp, ctypes.POINTER(ctypes.c_int64), vp, vp], i32),
         "afe_set_boundary_states": ([vp, vp], i32),
+        "afe_set_boundary_gradients": ([vp, vp], i32),
         "afe_subgrid_sizes": ([ctypes.POINTER(_Mesh), i32, vp], i32),
         "afe_subgrid_host": ([ctypes.POINTER(_Mesh), i32, vp, vp, vp, vp, vp, vp, vp], i32),
         "afe_last_error": ([], ctypes.c_char_p),
@@ -373,6 +374,18 @@ class CellData:
                 raise ValueError(f"boundary states must have shape ({count.value}, {self.N + 1}, 5)")
         self._bstate = prim
         _check(_lib.afe_set_boundary_states(self._h, None if prim is None else _dev(prim)))
+
+    def set_boundary_gradients(self, grad) -> None:
+        """Register the gradients of the Dirichlet data, d prim_k / d x_d,
+        device [count, N + 1, 3, 5] (needed with viscosity or heat
+        conduction; None unregisters); kept and refilled like the states."""
+        if grad is not None:
+            count = ctypes.c_int64()
+            _check(_lib.afe_boundary_nodes(self._h, ctypes.byref(count), None, None))
+            if tuple(grad.shape) != (count.value, self.N + 1, 3, 5):
+                raise ValueError(f"boundary gradients must have shape ({count.value}, {self.N + 1}, 3, 5)")
+        self._bgrad = grad
+        _check(_lib.afe_set_boundary_gradients(self._h, None if grad is None else _dev(grad)))
 
     def predictor_state(self, stream=None):
         import torch

@@ -241,6 +241,9 @@ afe_status check_params(const afe_params *p) {
 afe_status check_boundary(const afe_cell_data *cd) {
     if (cd->host.n_btri > 0 && !cd->g.bstate)
         return fail(AFE_E_ARG, "bounded mesh: no boundary states registered (afe_set_boundary_states)");
+    const afe_params &p = cd->params;
+    if (cd->host.n_btri > 0 && (p.mu != 0.0 || p.kappa != 0.0 || p.av) && !cd->g.bgrad)
+        return fail(AFE_E_ARG, "bounded viscous mesh: no boundary gradients registered (afe_set_boundary_gradients)");
     return AFE_OK;
 }
 
@@ -671,10 +674,6 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     cd->params = *params;
     const afe::HostGrid &h = cd->host;
     const int depth = params->accel_depth;
-    if (h.n_btri > 0 && (params->mu != 0.0 || params->kappa != 0.0 || params->av)) {
-        delete cd;
-        return fail(AFE_E_ARG, "a bounded mesh takes the Euler equations only (mu = kappa = 0, no artificial viscosity)");
-    }
     if (h.n_cells >= afe::kMaxCellsPerSlot) {
         delete cd;
         return fail(AFE_E_ARG, "too many cells");
@@ -709,6 +708,7 @@ afe_status build_afe_cell_data(const afe_mesh *mesh, int32_t N, const afe_params
     g.mixed = params->precision == AFE_MIXED ? 1 : 0;
     g.guess = params->predictor_guess;
     g.bstate = nullptr;
+    g.bgrad = nullptr;
     g.n_btri = h.n_btri;
     std::vector<int64_t> minv_ptr(h.n_cells + 1, 0), minv32_ptr(h.n_cells + 1, 0);
     for (int c = 0; c < h.n_cells; ++c) {
@@ -966,6 +966,13 @@ afe_status afe_set_boundary_states(afe_cell_data *cd, const double *prim) {
     if (!cd) return fail(AFE_E_ARG, "null argument");
     if (prim && cd->host.n_btri == 0) return fail(AFE_E_ARG, "the mesh has no boundary faces");
     cd->g.bstate = prim;
+    return AFE_OK;
+}
+
+afe_status afe_set_boundary_gradients(afe_cell_data *cd, const double *grad) {
+    if (!cd) return fail(AFE_E_ARG, "null argument");
+    if (grad && cd->host.n_btri == 0) return fail(AFE_E_ARG, "the mesh has no boundary faces");
+    cd->g.bgrad = grad;
     return AFE_OK;
 }
 

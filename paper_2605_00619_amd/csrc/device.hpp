@@ -74,6 +74,9 @@ struct DevGrid {
     // boundary face node b * nf + j and time node a, [n_btri * nf][nt][5]
     // (caller-owned; null when none are registered)
     const double *bstate;
+    // their gradients d prim_k / d x_d, [n_btri * nf][nt][3][5] (caller-owned;
+    // needed with viscosity or heat conduction)
+    const double *bgrad;
     int64_t n_btri;
     const double *h, *vol;    // [n_cells]
     const double *mrow;       // [ndof]

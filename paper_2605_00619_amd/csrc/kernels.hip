@@ -1584,22 +1584,37 @@ __global__ void __launch_bounds__(256) k_round_update(const DevSlot *__restrict_
 
 // Outside trace of a boundary face node of a bounded mesh from the Dirichlet
 // data: the exact state q_a at the predictor's time nodes (primitive, from
-// g.bstate), qbar = dt sum_a w_a q_a and Fbar_x = dt sum_a w_a F_x(q_a) with
-// the Euler flux, laid out as a trace entry: qbar (5), Fbar (3 x 5).
+// g.bstate), qbar = dt sum_a w_a q_a and Fbar_x = dt sum_a w_a F_x(q_a, grad
+// q_a), laid out as a trace entry: qbar (5), Fbar (3 x 5).  With viscosity
+// mu (the inside cell's) or heat conduction the flux is the Navier-Stokes one
+// with the exact gradient (g.bgrad, primitive, turned into the conserved
+// variables' here); else the Euler flux.
 template <int N>
-__device__ inline void boundary_trace(const DevGrid &g, int64_t node, double dt, double tb[20]) {
+__device__ inline void boundary_trace(const DevGrid &g, int64_t node, double dt, double mu, double tb[20]) {
     constexpr int nt = N + 1;
 #pragma unroll
     for (int e = 0; e < 20; ++e) tb[e] = 0.0;
     const double *s = g.bstate + node * nt * 5;
     const double gam = g.gamma;
+    const bool viscous = (mu != 0.0 || g.kappa != 0.0) && g.bgrad != nullptr;
 #pragma unroll
     for (int a = 0; a < nt; ++a) {
         const double r = s[a * 5], vx = s[a * 5 + 1], vy = s[a * 5 + 2], vz = s[a * 5 + 3], p = s[a * 5 + 4];
         const double q[5] = {r, r * vx, r * vy, r * vz, p / (gam - 1.0) + 0.5 * r * (vx * vx + vy * vy + vz * vz)};
         double F[3][5];
-        const double gq[3][5] = {};
-        ns_flux<false>(q, gq, gam, 0.0, 0.0, g.cv, F);
+        double gq[3][5] = {};
+        if (viscous) {
+            const double *gw = g.bgrad + (node * nt + a) * 15;  // [d][k]
+            for (int d = 0; d < 3; ++d) {
+                const double gr = gw[d * 5], gu = gw[d * 5 + 1], gv = gw[d * 5 + 2], gz = gw[d * 5 + 3], gp = gw[d * 5 + 4];
+                gq[d][0] = gr;
+                gq[d][1] = vx * gr + r * gu;
+                gq[d][2] = vy * gr + r * gv;
+                gq[d][3] = vz * gr + r * gz;
+                gq[d][4] = gp / (gam - 1.0) + 0.5 * (vx * vx + vy * vy + vz * vz) * gr + r * (vx * gu + vy * gv + vz * gz);
+            }
+        }
+        ns_flux<true>(q, gq, gam, viscous ? mu : 0.0, viscous ? g.kappa : 0.0, g.cv, F);
         const double wa = g.ref->w[a];
 #pragma unroll
         for (int v = 0; v < 5; ++v) {
@@ -1638,7 +1653,7 @@ __global__ void __launch_bounds__(256) k_face(DevGrid g, DevWork w, int which) {
 #pragma unroll
             for (int e = 0; e < 20; ++e) to[e] = tr[e];
         } else {
-            boundary_trace<N>(g, (-1 - kn) * nf + j, dt, to);
+            boundary_trace<N>(g, (-1 - kn) * nf + j, dt, w.mu_cell[g.sub_cell[k]], to);
         }
         const double *T = g.tri + k * 4;
         a2 = T[0];
