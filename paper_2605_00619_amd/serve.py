@@ -13,8 +13,11 @@ States stay resident on the device from setup to completion.
 
 Latency of a request = completion - arrival, split into queue (waiting for
 admission), setup and solve.  The scheduling logic talks to a backend
-(estimate / setup / attach / step / release) so that it can be exercised
-without a GPU; GpuBackend is the libafe one.
+(estimate / setup / attach / step / release, and discard for a set-up
+request that the batch refused) so that it can be exercised without a GPU;
+GpuBackend is the libafe one.  A request whose set-up or join fails is
+retired with the error's status and its memory returned to the budget; the
+rest of the batch keeps running.
 """
 from __future__ import annotations
 
@@ -125,6 +128,10 @@ class GpuBackend:
         cd.close()
         return state, cd.ndof
 
+    def discard(self, handle):
+        """Frees a set-up request that never joined the batch."""
+        handle[0].close()
+
     def ndof(self, handle) -> int:
         return handle[0].ndof
 
@@ -191,7 +198,15 @@ class Server:
                         used -= est[r.rid]
                         continue
                     res.ndof = self.be.ndof(handle)
-                    active[self.be.attach(handle, r)] = (r, handle, res)
+                    try:
+                        slot = self.be.attach(handle, r)
+                    except Exception as e:  # noqa: BLE001 - a refused join fails its request only
+                        res.status = getattr(e, "name", type(e).__name__)
+                        res.done = res.ready
+                        self.be.discard(handle)
+                        used -= est[r.rid]
+                        continue
+                    active[slot] = (r, handle, res)
                 if not active:
                     nxt = [waiting[0].arrival - (self.clock() - t0)] if waiting else []
                     wait = min([0.002] + [t for t in nxt if t > 0])

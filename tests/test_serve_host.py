@@ -26,6 +26,10 @@ class Clock:
             self.t += dt
 
 
+class _Refused(Exception):
+    name = "AFE_E_ARG"
+
+
 class FakeBackend:
     """Each request's mesh dict carries its byte size, DOF count, the step at
     which it fails (if any); a step takes 10 ms of virtual time."""
@@ -50,6 +54,8 @@ class FakeBackend:
         return req.mesh["ndof"]
 
     def attach(self, req, _):
+        if req.mesh.get("refuse"):
+            raise _Refused()
         slot = self.next_slot
         self.next_slot += 1
         self.live[slot] = (req, req.mesh["bytes"])
@@ -76,9 +82,13 @@ class FakeBackend:
         self.log.append((self.clock(), "leave", req.rid))
         return None, req.mesh["ndof"]
 
+    def discard(self, req):
+        self.log.append((self.clock(), "discard", req.rid))
 
-def _req(rid, arrival, nbytes, steps, ndof=100, fail_at=None):
-    return Request(rid, arrival, dict(bytes=nbytes, ndof=ndof, fail_at=fail_at), 2, steps, 0.1, lambda x: x)
+
+def _req(rid, arrival, nbytes, steps, ndof=100, fail_at=None, refuse=False):
+    return Request(rid, arrival, dict(bytes=nbytes, ndof=ndof, fail_at=fail_at, refuse=refuse), 2, steps, 0.1,
+                   lambda x: x)
 
 
 def _serve(reqs, budget, max_active=64):
@@ -128,6 +138,20 @@ def test_slot_limit_and_rejection_and_failure():
     assert len(be.live) == 0
     # the third request waited for a slot, not for memory
     assert res[2].queue > 0.0
+
+
+def test_refused_join_fails_only_its_request():
+    """A set-up request the batch refuses to join (a bounded mesh, which
+    batches do not take) is retired with the refusal's status, freed, and its
+    memory returned; the other requests run to completion."""
+    reqs = [_req(0, 0.0, 40, 4), _req(1, 0.0, 50, 4, refuse=True), _req(2, 0.001, 50, 4)]
+    res, be, srv = _serve(reqs, budget=100)
+    assert res[1].status == "AFE_E_ARG" and res[1].steps_done == 0
+    assert res[1].done == res[1].ready
+    assert [r.status for r in (res[0], res[2])] == ["AFE_OK", "AFE_OK"]
+    assert [r.steps_done for r in (res[0], res[2])] == [4, 4]
+    assert [rid for _, ev, rid in be.log if ev == "discard"] == [1]
+    assert len(be.live) == 0
 
 
 class _FailingLib:
