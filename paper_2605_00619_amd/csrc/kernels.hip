@@ -716,10 +716,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
         double q[5] = {1, 0, 0, 0, 1};
         int64_t l = 0;
         if (valid) {
-            for (int i = 0; i < 9; ++i) G[i] = g.geo[k * 10 + i];
+            // every load of the item is issued here, through global-address
+            // pointers: generic loads after the LDS writes below would each
+            // wait for those writes and for one another
+            const gptr<double> geo = (gptr<double>)(g.geo + k * 10);
+            for (int i = 0; i < 9; ++i) G[i] = geo[i];
             mu_c = w.mu_cell[c];
             l = g.dof_ptr[c] + g.conn[k * np + m];
-            for (int v = 0; v < 5; ++v) q[v] = w.x[l * nc + a * 5 + v];
+            if (MIXED) {
+                // g_a at node m: the mass term's inner block, from the node's
+                // row of the iterate (all time nodes) and the DOF-major u^n
+                double xr[nt * 5], ur[5], kt[nt];
+                const gptr<double> xg = (gptr<double>)(w.x + l * nc);
+                const gptr<double> ug = (gptr<double>)(w.un5 + l * 5);
+                const gptr<double> kg = (gptr<double>)(g.ref->Ktau + a * nt);
+                for (int i = 0; i < nt * 5; ++i) xr[i] = xg[i];
+                for (int v = 0; v < 5; ++v) ur[v] = ug[v];
+                for (int b = 0; b < nt; ++b) kt[b] = kg[b];
+                const double rw = 1.0 / ((gptr<double>)g.ref->w)[a];
+                for (int v = 0; v < 5; ++v) q[v] = xg[a * 5 + v];  // not xr[]: a is per thread
+                for (int v = 0; v < 5; ++v) {
+                    const double un = ur[v];
+                    double acc = 0.0;
+                    for (int b = 0; b < nt; ++b) acc += kt[b] * (xr[b * 5 + v] - un);
+                    fT[3 * np + m][lds_swz<C::pair>(3 * np + m, (s * nt + a) * 5 + v)] = rw * acc;
+                }
+            } else {
+                const gptr<double> xg = (gptr<double>)(w.x + l * nc + a * 5);
+                for (int v = 0; v < 5; ++v) q[v] = xg[v];
+            }
             if (QS)
                 for (int v = 0; v < 5; ++v) qs[QS ? s : 0][QS ? a : 0][QS ? m : 0][v] = q[v];
         }
@@ -729,23 +754,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
             node_flux<N, VISC>(Dt, qs[QS ? s : 0][QS ? a : 0], m, G, q, g.gamma, mu_c, g.kappa, g.cv, dt, fst, F);
             for (int d = 0; d < 3; ++d)
                 for (int v = 0; v < 5; ++v) fT[d * np + m][lds_swz<C::pair>(d * np + m, (s * nt + a) * 5 + v)] = fst[d * 5 + v];
-            if (MIXED) {
-                // g_a at node m: the mass term's inner block, from the node's
-                // row of the iterate (all time nodes) and the DOF-major u^n
-                const double rw = 1.0 / g.ref->w[a];
-                const double *xr = w.x + l * nc;
-                const double *ur = w.un5 + l * 5;
-                for (int v = 0; v < 5; ++v) {
-                    const double un = ur[v];
-                    double acc = 0.0;
-                    for (int b = 0; b < nt; ++b) acc += g.ref->Ktau[a * nt + b] * (xr[b * 5 + v] - un);
-                    fT[3 * np + m][lds_swz<C::pair>(3 * np + m, (s * nt + a) * 5 + v)] = rw * acc;
-                }
-            }
         }
         __syncthreads();
         const gptr<double> Kf = (gptr<double>)uni_ptr(MIXED ? g.ref->KMfrag : g.ref->Kfrag) + lane;
         for (int ctile = wv; ctile < C::ct; ctile += 4) {
+            // a lane's D column is the same for all its outputs: one factor
+            // w_a |J| per lane, loaded before the products
+            const int col = 16 * ctile + mf_d_col(lane, 0);
+            const int ss = col / (nt * 5), aa = (col / 5) % nt, vv = col % 5;
+            const int64_t kk = s0 + int64_t(chunk) * spb + ss;
+            const bool colok = col < C::cols && kk < s1;
+            const double fac = colok ? ((gptr<double>)g.ref->w)[aa] * ((gptr<double>)g.geo)[kk * 10 + 9] : 0.0;
             dbl4 acc[C::mt];
 #pragma unroll
             for (int mtile = 0; mtile < C::mt; ++mtile) acc[mtile] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -758,17 +777,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
                     acc[mtile] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kf[(mtile * C::ks + kst) * kWave], bv, acc[mtile], 0,
                                                                       0, 0);
             }
+            if (colok) {
+                double *out = w.rk + kk * np * nc + aa * 5 + vv;
 #pragma unroll
-            for (int mtile = 0; mtile < C::mt; ++mtile)
+                for (int mtile = 0; mtile < C::mt; ++mtile)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = 16 * mtile + mf_d_row(lane, r), col = 16 * ctile + mf_d_col(lane, r);
-                    if (row >= np || col >= C::cols) continue;
-                    const int ss = col / (nt * 5), aa = (col / 5) % nt, vv = col % 5;
-                    const int64_t kk = s0 + int64_t(chunk) * spb + ss;
-                    if (kk >= s1) continue;
-                    w.rk[(kk * np + row) * nc + aa * 5 + vv] = g.ref->w[aa] * g.geo[kk * 10 + 9] * acc[mtile][r];
-                }
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * mtile + mf_d_row(lane, r);
+                        if (row < np) out[row * nc] = fac * acc[mtile][r];
+                    }
+            }
         }
         __syncthreads();  // LDS is rewritten by the next item
     }
