@@ -435,6 +435,10 @@ afe_status launch_early_post(Engine &E, int it, const std::vector<int> &upper, h
 // predictor kernels read u^n of listed cells only, which this pass leaves
 // alone; the pass a cell falls in does not change its bits.
 constexpr int64_t kLateCorrectFraction = 256;
+// Grid of that pass's M^-1 update, in workgroups (two per CU): a full grid
+// would fill every CU ahead of the few-cell launches of the iteration tail it
+// overlaps.  Measured against 256 and 1024 and the full grid.
+constexpr int kSideMinvBlocks = 512;
 
 afe_status launch_early_correct(Engine &E, int it, const std::vector<int> &upper, hipStream_t s) {
     for (auto &gr : E.groups)
@@ -454,7 +458,7 @@ afe_status launch_early_correct(Engine &E, int it, const std::vector<int> &upper
         for (int sl : gr.slots) {
             afe_cell_data *cd = E.cds[sl];
             HIP_TRY(afe::launch_pred_post(cd->g, E.tab[sl].w, 1, E.side));
-            HIP_TRY(afe::launch_correct(cd->g, E.tab[sl].w, E.u[sl], 0, E.side));
+            HIP_TRY(afe::launch_correct(cd->g, E.tab[sl].w, E.u[sl], 0, E.side, kSideMinvBlocks));
         }
     HIP_TRY(hipEventRecord(E.ev_early, E.side));
     E.forked2 = true;

@@ -217,7 +217,9 @@ hipError_t launch_mark_late2(const DevSlot *tab, const int32_t *list, int count,
 hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, int which, hipStream_t s);
 // Corrector (faces, right-hand side, M^-1 update of u, positivity) for the
 // cells with late2[c] == which.
-hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, int which, hipStream_t s);
+// max_blocks > 0 caps the grid of the M^-1 update (its items are then strided).
+hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, int which, hipStream_t s,
+                          int max_blocks = 0);
 // Predictor iteration counts of the step into status[4..7].
 hipError_t launch_step_stats(const DevGrid &g, const DevWork &w, hipStream_t s);
 // Physical coordinates of the error-norm quadrature points of every sub-tet,

@@ -1064,15 +1064,19 @@ __global__ void __launch_bounds__(256) k_round_minv(const DevSlot *__restrict__ 
     }
 }
 
-// Corrector: u += M_i^{-1} rhs for every cell of one simulation.
+// Corrector: u += M_i^{-1} rhs for every cell of one simulation, work item =
+// (cell, 64-row tile); a grid smaller than the item count strides over them.
 template <int NC>
 __global__ void __launch_bounds__(256) k_minv_update(DevGrid g, const double *__restrict__ X, double *__restrict__ Y,
                                                      int tpc, const int32_t *__restrict__ late2, int which) {
     __shared__ double part[NC][kWave];
-    const int lb = xcd_block();
-    if (late2[lb / tpc] != which) return;
-    const int c = lb / tpc;
-    minv_tile<NC, 1>(g, c, lb % tpc, 0, int(g.dof_ptr[c + 1] - g.dof_ptr[c]), X, Y, nullptr, part);
+    const int n_items = g.n_cells * tpc;
+    for (int lb = xcd_block(); lb < n_items; lb += gridDim.x) {
+        const int c = lb / tpc;
+        if (late2[c] != which) continue;
+        minv_tile<NC, 1>(g, c, lb % tpc, 0, int(g.dof_ptr[c + 1] - g.dof_ptr[c]), X, Y, nullptr, part);
+        __syncthreads();  // part is rewritten by the next item
+    }
 }
 
 // Mixed precision: S = D (A32 (D R)) with the FP32 scaled inverse A32 and the
@@ -2039,15 +2043,16 @@ hipError_t launch_pred_post(const DevGrid &g, const DevWork &w, int which, hipSt
     });
 }
 
-hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, int which, hipStream_t s) {
+hipError_t launch_correct(const DevGrid &g, const DevWork &w, double *u, int which, hipStream_t s, int max_blocks) {
     return dispatch(g.N, [&](auto n) {
         constexpr int NN = decltype(n)::value;
         using D = Dim<NN>;
         hipLaunchKernelGGL(k_face<NN>, dim3(blocks_for(g.nsub, 256 / D::nf)), dim3(256), 0, s, g, w, which);
         hipLaunchKernelGGL(k_rhs<NN>, dim3(blocks_for(g.ndof * 5, 256)), dim3(256), 0, s, g, w, which);
         const int tpc = (g.max_cell_dofs + 63) / 64;
-        hipLaunchKernelGGL(k_minv_update<5>, dim3(unsigned(g.n_cells) * tpc), dim3(256), 0, s, g, w.rhs, u, tpc,
-                           w.late2, which);
+        unsigned blocks = unsigned(g.n_cells) * tpc;
+        if (max_blocks > 0) blocks = std::min(blocks, unsigned(max_blocks));
+        hipLaunchKernelGGL(k_minv_update<5>, dim3(blocks), dim3(256), 0, s, g, w.rhs, u, tpc, w.late2, which);
         hipLaunchKernelGGL(k_positivity, dim3(blocks_for(g.ndof, 256)), dim3(256), 0, s, g, w, u, which);
         return hipGetLastError();
     });
