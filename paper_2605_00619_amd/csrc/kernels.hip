@@ -905,6 +905,15 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
     const int64_t k0 = int64_t(blockIdx.x) * spb;
     const gptr<double> Vf = (gptr<double>)uni_ptr(g.ref->Vfrag) + lane;
     for (int ctile = wv; ctile < ct; ctile += 4) {
+        // a lane's D column (sub-tet, variable) is the same for all its
+        // outputs: whether it is written, and its factor |J|, loaded before
+        // the products
+        const int col = 16 * ctile + mf_d_col(lane, 0);
+        const int ss = col / 5, vv = col % 5;
+        const int64_t kk = k0 + ss;
+        bool colok = col < cols && kk < g.nsub;
+        if (colok) colok = w.late[g.sub_cell[kk]] == which;
+        const double fac = colok ? ((gptr<double>)g.geo)[kk * 10 + 9] : 0.0;
         dbl4 acc[mt];
 #pragma unroll
         for (int mtile = 0; mtile < mt; ++mtile) acc[mtile] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -916,34 +925,34 @@ __global__ void __launch_bounds__(Dim<N>::threads) k_subtet_post(DevGrid g, DevW
             for (int mtile = 0; mtile < mt; ++mtile)
                 acc[mtile] = __builtin_amdgcn_mfma_f64_16x16x4f64(Vf[(mtile * ks + kst) * kWave], bv, acc[mtile], 0, 0, 0);
         }
+        if (colok) {
+            double *out = w.vk + kk * np * 5 + vv;
 #pragma unroll
-        for (int mtile = 0; mtile < mt; ++mtile)
+            for (int mtile = 0; mtile < mt; ++mtile)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = 16 * mtile + mf_d_row(lane, r), col = 16 * ctile + mf_d_col(lane, r);
-                if (row >= np || col >= cols) continue;
-                const int ss = col / 5, vv = col % 5;
-                const int64_t kk = k0 + ss;
-                if (kk >= g.nsub) continue;
-                const int cc = g.sub_cell[kk];
-                if (w.late[cc] != which) continue;
-                w.vk[(kk * np + row) * 5 + vv] = g.geo[kk * 10 + 9] * acc[mtile][r];
-            }
+                for (int r = 0; r < 4; ++r) {
+                    const int row = 16 * mtile + mf_d_row(lane, r);
+                    if (row < np) out[row * 5] = fac * acc[mtile][r];
+                }
+        }
     }
     if (!valid) return;
     if (a == 1 || nt == 1) {
-        // traces at face nodes
+        // traces at face nodes (the weights in registers: the stores below
+        // could otherwise alias them and force a reload after each)
         if (m < nf) {
             const int j = m, mm = g.ref->fn[j];
+            double wb[nt];
+            for (int b = 0; b < nt; ++b) wb[b] = ((gptr<double>)g.ref->w)[b];
             double *out = w.trace + (k * nf + j) * 20;
             for (int v = 0; v < 5; ++v) {
                 double acc = 0.0;
-                for (int b = 0; b < nt; ++b) acc += g.ref->w[b] * qs[s][b][mm][v];
+                for (int b = 0; b < nt; ++b) acc += wb[b] * qs[s][b][mm][v];
                 out[v] = dt * acc;
             }
             for (int i = 0; i < 15; ++i) {
                 double acc = 0.0;
-                for (int b = 0; b < nt; ++b) acc += g.ref->w[b] * fs[s][b][mm][i];
+                for (int b = 0; b < nt; ++b) acc += wb[b] * fs[s][b][mm][i];
                 out[5 + i] = dt * acc;
             }
         }
