@@ -798,14 +798,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 constexpr int kGatherBatch = 16;
 __device__ inline double ordered_gather_sum(const double *__restrict__ p, const int32_t *__restrict__ idx, int q0,
                                             int q1, int stride, int col) {
+    const gptr<double> pg = (gptr<double>)p;
+    const gptr<int32_t> ig = (gptr<int32_t>)idx;
     double acc = 0.0;
     for (int q = q0; q < q1; q += kGatherBatch) {
+        // index loads without a branch each (past the end the last entry is
+        // read again), so that they are in flight together
         int32_t ix[kGatherBatch];
 #pragma unroll
-        for (int u = 0; u < kGatherBatch; ++u) ix[u] = q + u < q1 ? idx[q + u] : 0;
+        for (int u = 0; u < kGatherBatch; ++u) ix[u] = ig[min(q + u, q1 - 1)];
         double v[kGatherBatch];
 #pragma unroll
-        for (int u = 0; u < kGatherBatch; ++u) v[u] = q + u < q1 ? p[int64_t(ix[u]) * stride + col] : 0.0;
+        for (int u = 0; u < kGatherBatch; ++u) v[u] = q + u < q1 ? pg[int64_t(ix[u]) * stride + col] : 0.0;
 #pragma unroll
         for (int u = 0; u < kGatherBatch; ++u)
             if (q + u < q1) acc += v[u];
