@@ -1205,6 +1205,22 @@ __device__ inline HT *hist_col(const DevGrid &g, const DevWork &w, double *in_pl
     return pl + int64_t(w.pool_slot[c]) * g.pool_stride + int64_t(s - g.hist_small) * len;
 }
 
+// The same, with the cell's history layout read once (the pool slot of a
+// cell does not change while its columns are read), so that a column's
+// address is arithmetic and many columns' loads can be in flight together.
+struct HistLayout {
+    int small;
+    int64_t ip_off, pool_off, len;
+    __device__ HistLayout(const DevGrid &g, const DevWork &w, int c, int64_t base, int64_t len_)
+        : small(g.hist_small), ip_off(base * g.hist_small), pool_off(int64_t(w.pool_slot[c]) * g.pool_stride),
+          len(len_) {}
+    template <typename HT>
+    __device__ const HT *col(const double *in_place, const double *pool, int s) const {
+        const HT *ip = reinterpret_cast<const HT *>(in_place), *pl = reinterpret_cast<const HT *>(pool);
+        return s < small ? ip + ip_off + int64_t(s) * len : pl + pool_off + int64_t(s - small) * len;
+    }
+};
+
 // history bookkeeping: (count kept, head slot) after the drop this iteration makes
 __device__ inline void ring_state(const DevWork &w, int c, int &k, int &head, bool &dropped) {
     k = w.hist[2 * c];
@@ -1221,12 +1237,14 @@ __device__ inline void ring_state(const DevWork &w, int c, int &k, int &head, bo
 // Tiles of 64 DOFs per cell in the partials buffer of a simulation.
 __device__ inline int part_tiles(const DevGrid &g) { return (g.max_cell_dofs + 63) / 64; }
 
-// History columns per pass of the dot products: kDotCols, or kDotColsWide in
-// the instance launched on short lists (fewer passes, each a round trip to
-// memory; more registers, which only the short lists can afford).  Each
-// column's sum is the same either way.
+// History columns per pass of the dot products: kDotCols, or in the instance
+// launched on short lists kDotColsWide (FP32 history) / kDotColsWide64 (FP64
+// history): fewer passes, each a round trip to memory, for more registers,
+// which only the short lists can afford (16 FP64 columns would take 208
+// VGPRs).  Each column's sum is the same either way.
 constexpr int kDotCols = 4;
 constexpr int kDotColsWide = 16;
+constexpr int kDotColsWide64 = 8;
 
 template <int N, int DC, typename HT>
 __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, int tile, double (*accs)[4]) {
@@ -1310,26 +1328,39 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
     }
     if (hist_on) {
         // DC history columns per pass, so that their loads are in flight together
+        // Column addresses from the layout read once, and loads with neither a
+        // branch nor a data-dependent address: past the last column, in-place
+        // slot 0 is read and its value not used; past the tile's last element,
+        // its first is read and d = dfe = fe = 0 adds +0 (the sums start at +0
+        // and cannot become -0, so they keep their bits).
+        const HistLayout hl(g, w, c, base, len);
+        const gptr<double> dFa = (gptr<double>)w.dF, dFpa = (gptr<double>)w.dFp;
         for (int j0 = 0; j0 <= k; j0 += DC) {
             double ph[DC], pb[DC];
+            const HT *cols[DC];
 #pragma unroll
-            for (int u = 0; u < DC; ++u) ph[u] = pb[u] = 0.0;
+            for (int u = 0; u < DC; ++u) {
+                ph[u] = pb[u] = 0.0;
+                cols[u] = uni_ptr(hl.col<HT>((const double *)dFa, (const double *)dFpa, j0 + u < k ? (head + j0 + u) % depth : 0));
+            }
 #pragma unroll
             for (int q = 0; q < kPer; ++q) {
-                if (ie[q] < e1) {
-                    double d[DC];
+                const bool in = ie[q] < e1;
+                const int64_t e = in ? ie[q] : e0;
+                double d[DC];
 #pragma unroll
-                    for (int u = 0; u < DC; ++u) {
-                        const int j = j0 + u;
-                        d[u] = j < k ? double(hist_col<HT>(g, w, w.dF, w.dFp, c, base, len, (head + j) % depth)[ie[q]])
-                                     : dfe[q];
-                    }
-#pragma unroll
-                    for (int u = 0; u < DC; ++u) {
-                        ph[u] = fma(d[u], dfe[q], ph[u]);
-                        pb[u] = fma(d[u], fe[q], pb[u]);
-                    }
+                for (int u = 0; u < DC; ++u) {
+                    const double h = double(((const __attribute__((address_space(1))) HT *)cols[u])[e]);
+                    d[u] = (in && j0 + u < k) ? h : dfe[q];
                 }
+#pragma unroll
+                for (int u = 0; u < DC; ++u) {
+                    ph[u] = fma(d[u], dfe[q], ph[u]);
+                    pb[u] = fma(d[u], fe[q], pb[u]);
+                }
+                // FP64 history: one element's columns in flight at a time (all of
+                // them would cost the short-list instance an occupancy step)
+                if (sizeof(HT) == 8) __builtin_amdgcn_sched_barrier(0);
             }
 #pragma unroll
             for (int u = 0; u < DC; ++u) {
@@ -2004,7 +2035,7 @@ hipError_t launch_pred_round(const RoundArgs &a, hipStream_t s) {
         if (a.ev1) (void)hipEventRecord(a.ev1, s);
         auto dots = a.mixed ? (a.upd_fine && a.n_upper >= 0 ? k_round_dots<NN, kDotColsWide, float>
                                                            : k_round_dots<NN, kDotCols, float>)
-                            : (a.upd_fine && a.n_upper >= 0 ? k_round_dots<NN, kDotColsWide, double>
+                            : (a.upd_fine && a.n_upper >= 0 ? k_round_dots<NN, kDotColsWide64, double>
                                                            : k_round_dots<NN, kDotCols, double>);
         hipLaunchKernelGGL(dots, grid(a.shape.g_dots, tpc), dim3(256), 0, s, a.tab, a.list, a.count, tpc);
         hipLaunchKernelGGL(k_round_solve, grid(a.shape.g_solve, 1), dim3(kWave), 0, s, a.tab, a.list, a.count, a.next,
