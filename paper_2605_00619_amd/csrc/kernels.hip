@@ -1328,11 +1328,11 @@ __device__ inline void and_dots_tile(const DevGrid &g, const DevWork &w, int c, 
     }
     if (hist_on) {
         // DC history columns per pass, so that their loads are in flight together
-        // Column addresses from the layout read once, and loads with neither a
-        // branch nor a data-dependent address: past the last column, in-place
-        // slot 0 is read and its value not used; past the tile's last element,
-        // its first is read and d = dfe = fe = 0 adds +0 (the sums start at +0
-        // and cannot become -0, so they keep their bits).
+        // Column addresses from the layout read once, and loads without a
+        // branch each: past the last column, in-place slot 0 is read and its
+        // value not used; past the tile's last element, its first is read and
+        // d = dfe = fe = 0 adds +0 (the sums start at +0 and cannot become -0,
+        // so they keep their bits).
         const HistLayout hl(g, w, c, base, len);
         const gptr<double> dFa = (gptr<double>)w.dF, dFpa = (gptr<double>)w.dFp;
         for (int j0 = 0; j0 <= k; j0 += DC) {
